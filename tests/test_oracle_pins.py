@@ -1,0 +1,305 @@
+"""Pins the FP64 oracle to facts that do not come from the oracle itself:
+algebraic identities between gate matrices, an independent tensor-contraction
+simulator for small n, closed forms (GHZ, QFT of a basis state, RY + CZ
+expectations), circuit-then-inverse, norm preservation and the virtual-swap
+layout rule.  CPU only."""
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import oracle as orc
+from oracle import mlp_oracle as mlp
+from workloads import circuits as W
+
+TOL = 1e-13
+
+
+def M(kind, *params, dense=None):
+    return orc.gate_matrix(kind, params, dense=dense)
+
+
+I2 = np.eye(2)
+
+
+def close(a, b, tol=TOL):
+    return np.max(np.abs(np.asarray(a) - np.asarray(b))) <= tol
+
+
+# ---------------------------------------------------------------- matrices --
+
+@pytest.mark.parametrize("kind", ["h", "x", "y", "z", "s", "sdg", "t", "tdg", "sx"])
+def test_fixed_gates_unitary(kind):
+    u = M(kind)
+    assert close(u.conj().T @ u, np.eye(2))
+
+
+def test_pauli_and_clifford_identities():
+    X, Y, Z, H, S, T = M("x"), M("y"), M("z"), M("h"), M("s"), M("t")
+    assert close(X @ X, I2) and close(Y @ Y, I2) and close(Z @ Z, I2)
+    assert close(X @ Y, 1j * Z)            # Pauli algebra fixes the sign of Y
+    assert close(H @ X @ H, Z) and close(H @ Z @ H, X)
+    assert close(S @ S, Z) and close(T @ T, S)
+    assert close(M("sdg"), S.conj().T) and close(M("tdg"), T.conj().T)
+    assert close(M("sx") @ M("sx"), X)
+    assert close(Z, np.diag([1, -1]))      # |0> is the +1 eigenvector of Z
+    assert close(H @ np.array([1, 0]), np.array([1, 1]) / np.sqrt(2))
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.3, 1.7, np.pi, 4.1, 2 * np.pi - 0.2])
+def test_rotations_are_pauli_exponentials(theta):
+    X, Y, Z = M("x"), M("y"), M("z")
+    assert close(M("rx", theta), scipy.linalg.expm(-0.5j * theta * X))
+    assert close(M("ry", theta), scipy.linalg.expm(-0.5j * theta * Y))
+    assert close(M("rz", theta), scipy.linalg.expm(-0.5j * theta * Z))
+    assert close(M("p", theta), np.exp(0.5j * theta) * M("rz", theta))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_u3_is_zyz(seed):
+    rng = np.random.default_rng(seed)
+    t, p, l = rng.uniform(0, 2 * np.pi, 3)
+    zyz = np.exp(0.5j * (p + l)) * M("rz", p) @ M("ry", t) @ M("rz", l)
+    assert close(M("u3", t, p, l), zyz)
+    assert close(M("u3", t, -np.pi / 2, np.pi / 2), M("rx", t))
+    assert close(M("u3", t, 0, 0), M("ry", t))
+
+
+def test_two_qubit_gates():
+    X, Z = M("x"), M("z")
+    P0, P1 = np.diag([1, 0]), np.diag([0, 1])
+    # index bit 0 <-> first listed qubit, so kron(op_on_q1, op_on_q0)
+    assert close(M("cx"), np.kron(I2, P0) + np.kron(X, P1))
+    assert close(M("cz"), np.kron(I2, P0) + np.kron(Z, P1))
+    for lam in (0.4, np.pi, 5.0):
+        assert close(M("cp", lam), np.kron(I2, P0) + np.kron(M("p", lam), P1))
+        assert close(M("rzz", lam), scipy.linalg.expm(-0.5j * lam * np.kron(Z, Z)))
+    assert close(M("cp", np.pi), M("cz"))
+    A, B = M("u3", 0.3, 1.1, 2.3), M("h")
+    sw = M("swap")
+    assert close(sw @ np.kron(A, B) @ sw, np.kron(B, A))
+
+
+def test_dense_passthrough_and_haar_unitarity():
+    rng = W.rng_for(11)
+    for k in range(1, 7):
+        u = W.haar_unitary(rng, 2 ** k)
+        assert np.max(np.abs(u.conj().T @ u - np.eye(2 ** k))) <= 1e-13
+        assert close(M("dense", dense=u), u)
+
+
+# ---------------------------------------------- independent small simulator --
+
+def tensor_apply(psi, n, u, qubits, controls=()):
+    """Independent reference: contract the gate with the state viewed as an
+    n-axis tensor (axis n-1-q holds qubit q), restricted to the slice where
+    every control qubit is 1."""
+    k = len(qubits)
+    t = psi.reshape([2] * n).copy()
+    ax = [n - 1 - q for q in qubits]
+    sl = [slice(None)] * n
+    for c in controls:
+        sl[n - 1 - c] = 1
+    sl = tuple(sl)
+    sub = t[sl]
+    # axes of `sub`: remove the control axes, keep order
+    remaining = [a for a in range(n) if not any(a == n - 1 - c for c in controls)]
+    sax = [remaining.index(a) for a in ax]
+    # u index bit j <-> qubit j; as a tensor: u[(r_{k-1}..r_0), (s_{k-1}..s_0)]
+    ut = u.reshape([2] * (2 * k))
+    # ut axes: out bits (k-1..0), in bits (k-1..0); qubit j's in-axis is 2k-1-j
+    in_axes = [2 * k - 1 - j for j in range(k)]
+    moved = np.tensordot(ut, sub, axes=(in_axes, sax))
+    # moved axes: out bits (k-1..0) then the untouched sub axes in order
+    out_pos = [k - 1 - j for j in range(k)]        # position of qubit j's out-axis
+    rest = [a for a in range(sub.ndim) if a not in sax]
+    order = [None] * sub.ndim
+    for j in range(k):
+        order[sax[j]] = out_pos[j]
+    for i, a in enumerate(rest):
+        order[a] = k + i
+    t[sl] = np.transpose(moved, order)
+    return t.reshape(-1)
+
+
+def kron_embed_1q(n, u, q):
+    """Full 2^n x 2^n matrix of a one-qubit gate by Kronecker products."""
+    full = np.array([[1.0 + 0j]])
+    for j in range(n - 1, -1, -1):
+        full = np.kron(full, u if j == q else I2)
+    return full
+
+
+def test_tensor_reference_matches_kronecker():
+    rng = np.random.default_rng(1)
+    n = 5
+    psi = rng.normal(size=2 ** n) + 1j * rng.normal(size=2 ** n)
+    u = M("u3", 0.7, 1.9, 2.6)
+    for q in range(n):
+        assert close(tensor_apply(psi, n, u, [q]), kron_embed_1q(n, u, q) @ psi, 1e-12)
+
+
+@pytest.mark.parametrize("n", [3, 5, 8])
+@pytest.mark.parametrize("seed", range(4))
+def test_oracle_matches_tensor_reference(n, seed):
+    c = W.random_mixed(seed * 31 + n, n, 60, max_dense_k=min(3, n))
+    rng = np.random.default_rng(seed)
+    psi0 = rng.normal(size=2 ** n) + 1j * rng.normal(size=2 ** n)
+    psi0 /= np.linalg.norm(psi0)
+    ref = psi0.copy()
+    for g in c.gates:
+        u = M(g.kind, *g.params, dense=g.matrix)
+        ref = tensor_apply(ref, n, u, list(g.qubits), list(g.controls))
+    got = orc.run(n, c.gates, psi=psi0)
+    assert np.max(np.abs(got - ref)) <= 1e-13
+
+
+def test_full_unitary_product_n4():
+    """Brute force: the ordered product of full embeddings, applied to e_0 and
+    to random states, equals the oracle's gate-by-gate result."""
+    n = 4
+    c = W.random_mixed(77, n, 30, max_dense_k=3)
+    U = np.eye(2 ** n, dtype=np.complex128)
+    for g in c.gates:
+        u = M(g.kind, *g.params, dense=g.matrix)
+        cols = [tensor_apply(np.eye(2 ** n)[:, j].astype(complex), n, u, list(g.qubits), list(g.controls))
+                for j in range(2 ** n)]
+        U = np.stack(cols, axis=1) @ U
+    rng = np.random.default_rng(3)
+    for trial in range(4):
+        psi = np.zeros(2 ** n, complex)
+        if trial == 0:
+            psi[0] = 1
+        else:
+            psi = rng.normal(size=2 ** n) + 1j * rng.normal(size=2 ** n)
+        assert np.max(np.abs(orc.run(n, c.gates, psi=psi) - U @ psi)) <= 1e-13
+
+
+# ------------------------------------------------------------- closed forms --
+
+@pytest.mark.parametrize("n", [2, 3, 7, 12, 16])
+def test_ghz(n):
+    psi = orc.run_circuit(W.ghz(n))
+    ref = np.zeros(2 ** n, complex)
+    ref[0] = ref[-1] = 1 / np.sqrt(2)
+    assert np.max(np.abs(psi - ref)) <= 1e-15
+    p = orc.probabilities(psi, list(range(n)))
+    assert abs(p[0] - 0.5) < 1e-15 and abs(p[-1] - 0.5) < 1e-15
+    assert np.max(np.abs(orc.expect_z(psi))) < 1e-15
+
+
+@pytest.mark.parametrize("n,x0", [(3, 5), (5, 19), (8, 201), (12, 3001), (14, 12345)])
+def test_qft_of_basis_state(n, x0):
+    psi = orc.run_circuit(W.qft(n, x0))
+    y = np.arange(2 ** n, dtype=np.int64)
+    phase = 2 * np.pi * ((x0 * y) % (2 ** n)) / 2 ** n     # integer product, no FP loss
+    ref = np.exp(1j * phase) / np.sqrt(2 ** n)
+    assert np.max(np.abs(psi - ref)) <= 1e-12
+    assert np.max(np.abs(np.abs(psi) - 2 ** (-n / 2))) <= 1e-13
+
+
+@pytest.mark.parametrize("n", [4, 9, 13])
+def test_ry_cz_ladder_expectations(n):
+    th = np.random.default_rng(n).uniform(0, 2 * np.pi, n)
+    psi = orc.run_circuit(W.ry_cz_ladder(n, th))
+    assert np.max(np.abs(orc.expect_z(psi) - np.cos(th))) <= 1e-13
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_circuit_then_inverse(seed):
+    n = 7
+    c = W.random_mixed(seed, n, 80, max_dense_k=4)
+    both = c.gates + W.inverse(c).gates
+    psi = orc.run(n, both, x0=c.x0)
+    ref = orc.basis_state(n, c.x0)
+    assert np.max(np.abs(psi - ref)) <= 1e-12
+
+
+def test_norm_preserved_and_measurements_independent():
+    n = 10
+    c = W.random_mixed(5, n, 120, max_dense_k=3)
+    psi = orc.run_circuit(c)
+    assert abs(orc.norm(psi) - 1.0) <= 1e-12
+    p = np.abs(psi) ** 2
+    assert abs(orc.norm(psi) - p.sum()) <= 1e-14
+    qs = [7, 2, 4]
+    t = p.reshape([2] * n)
+    keep = [n - 1 - q for q in qs]
+    marg = t.sum(axis=tuple(a for a in range(n) if a not in keep))
+    # marg axes are in increasing axis order = decreasing qubit order among qs
+    got = orc.probabilities(psi, qs).reshape([2] * len(qs))  # axes: bit2 (q=4), bit1 (q=2), bit0 (q=7)
+    srt = sorted(qs, reverse=True)                           # qubits in marg's axis order
+    perm = [srt.index(q) for q in reversed(qs)]
+    assert np.max(np.abs(np.transpose(marg, perm) - got)) <= 1e-14
+    z = orc.expect_z(psi)
+    for q in range(n):
+        bits = (np.arange(2 ** n) >> q) & 1
+        assert abs(z[q] - np.sum(p * (1 - 2 * bits))) <= 1e-13
+
+
+def test_virtual_swap_layout_rule():
+    """Dropping every SWAP and reading the result through the expected
+    logical-to-physical map gives the state of the circuit with SWAPs."""
+    n = 9
+    c = W.layered_u3_cx(3, n=n, depth=12, swap_frac=0.5)
+    assert any(g.kind == "swap" for g in c.gates)
+    with_swaps = orc.run_circuit(c)
+    # without swaps: relabel the remaining gates through the running map
+    l2p = np.arange(n)
+    relabelled = []
+    for g in c.gates:
+        if g.kind == "swap":
+            a, b = g.qubits
+            l2p[a], l2p[b] = l2p[b], l2p[a]
+        else:
+            relabelled.append(W.Gate(g.kind, tuple(int(l2p[q]) for q in g.qubits),
+                                     tuple(int(l2p[q]) for q in g.controls), g.params, g.matrix))
+    phys = orc.run(n, relabelled)
+    expected = orc.expected_layout(n, c.gates)
+    assert np.array_equal(expected, l2p)
+    assert np.max(np.abs(orc.logical_from_physical(phys, expected) - with_swaps)) <= 1e-13
+
+
+def test_oracle_rejects_bad_gates():
+    with pytest.raises(ValueError):
+        orc.run(3, [W.Gate("cx", (1, 1))])
+    with pytest.raises(ValueError):
+        orc.run(3, [W.Gate("h", (3,))])
+    with pytest.raises(ValueError):
+        orc.run(3, [W.Gate("x", (0,), controls=(0,))])
+
+
+# ------------------------------------------------------------------ MLP -----
+
+def test_mlp_gradients_match_finite_differences():
+    p = mlp.init_params(7)
+    rng = np.random.default_rng(0)
+    X = rng.normal(size=(9, 64))
+    t = rng.normal(size=9)
+    _, g = mlp.backward(p, X, t)
+    h = 1e-6
+    for name in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        flat = p[name].reshape(-1)
+        for idx in rng.choice(flat.size, size=min(6, flat.size), replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp = mlp.loss(p, X, t)
+            flat[idx] = old - h
+            lm = mlp.loss(p, X, t)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            an = g[name].reshape(-1)[idx]
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd)), (name, idx, fd, an)
+
+
+def test_adam_reduces_loss():
+    p = mlp.init_params(1)
+    rng = np.random.default_rng(1)
+    X = rng.normal(size=(64, 64))
+    t = X[:, 0] * 0.5 - X[:, 1]
+    m = {k: np.zeros_like(v) for k, v in p.items()}
+    v = {k: np.zeros_like(v) for k, v in p.items()}
+    l0 = mlp.loss(p, X, t)
+    for s in range(1, 201):
+        _, g = mlp.backward(p, X, t)
+        mlp.adam_step(p, g, m, v, s, 1e-3)
+    assert mlp.loss(p, X, t) < 0.1 * l0
