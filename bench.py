@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark of the simulation hot path on one MI355X.
+
+Default workload: a 30-qubit complex64 circuit of 200 Haar-random dense
+blocks (k ~ U{2..6} on seeded qubit subsets, seed 2).  One step = one run of
+the whole fused plan over the 2^30-amplitude state (tile passes with
+vector-ALU and matrix-core blocks) plus the FP64 <Z_i> reduction.  The plan is
+built once before the timed region (its host time is reported as plan_s).
+
+Prints ONE JSON line.  `value` is the step's algorithmic HBM throughput
+(sum over passes of 2 * 2^n * 8 bytes, plus the 2^n * 8 bytes the reduction
+reads, divided by the step time).  The roofline object describes the kernel
+that takes most of the step, timed live with HIP events on the simulator's
+stream; the CPU baseline is the FP64 oracle on a bounded sample of the same
+circuit.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+MFMA_F32_PEAK_TFLOPS = 157.3
+MFMA_F64_PEAK_TFLOPS = 78.6
+PASS_NAMES = {0: "tile_pass_kernel", 1: "tile_lds_kernel", 2: "state_lds_kernel", 3: "sweep_kernel",
+              4: "swap_bits_kernel"}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "planner.cpp"):
+        with open(os.path.join(ROOT, "paper_2410_09326_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def make_workload(name: str):
+    from workloads import circuits as W
+    if name == "haar30":
+        c = W.haar_blocks(2, n=30, nblocks=200)
+        return c, 0, "30-qubit circuit of 200 Haar-random dense blocks (k~U{2..6}, seed 2), complex64"
+    if name == "qft28":
+        c = W.qft_then_layers(1, n=28, layers=40)
+        return c, 0, "28-qubit QFT of a seeded basis state + 40 random U3/CZ layers, complex64, virtual swaps"
+    if name == "haar20":
+        c = W.haar_blocks(2, n=20, nblocks=200)
+        return c, 0, "20-qubit circuit of 200 Haar-random dense blocks (k~U{2..6}, seed 2), complex64"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def traffic_for(kernel: str, workload: str, launches_bytes: float):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(circ, seconds: float):
+    """The FP64 oracle (plain OpenMP loops, one pass per block) on the first
+    blocks of the same circuit until `seconds` of work have been done."""
+    import numpy as np
+    from oracle import oracle as orc
+    n = circ.n
+    psi = np.zeros(2 ** n, dtype=np.complex128)
+    psi[circ.x0] = 1.0
+    done = 0
+    t0 = time.perf_counter()
+    for g in circ.gates:
+        u = orc.gate_matrix(g.kind, g.params, dense=g.matrix)
+        orc.apply_matrix_inplace(n, psi, u, g.qubits)
+        done += 1
+        if time.perf_counter() - t0 > seconds:
+            break
+    el = time.perf_counter() - t0
+    bytes_c64 = done * 2.0 * (2 ** n) * 8
+    return {"value": bytes_c64 / el / 1e9, "unit": "GB/s", "cores": orc.num_threads(), "kind": "oracle",
+            "sample": f"first {done} of {len(circ.gates)} blocks at n={n} in FP64 ({el:.1f} s; bytes counted "
+                      f"as the complex64 path's 2*2^n*8 per block)", "seconds": el, "blocks": done}
+
+
+def main() -> None:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="haar30")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 2^30 x 8-byte device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this simulator has no multi-GPU path (state sharding is a design "
+              "note only); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2410_09326_amd as q
+
+    circ, prec, desc = make_workload(args.workload)
+    n = circ.n
+    amp = 8 if prec == q.C64 else 16
+    t0 = time.perf_counter()
+    plan = q.Plan(n, circ.gates, precision=prec)
+    plan_s = time.perf_counter() - t0
+    st = plan.stats()
+    passes = plan.passes()
+
+    sim = q.Simulator(n, prec)
+    sim.init_basis(circ.x0)
+    for _ in range(args.warmup):
+        sim.run(plan)
+        sim.expect_z()
+    torch.cuda.synchronize()
+
+    recs_all = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        prof = sim.profile(plan)          # the plan, with HIP events around every pass
+        recs_all.append(prof.records())
+        z = sim.expect_z()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms = el / args.steps * 1e3
+    norm = sim.norm()
+
+    if args.copy_calibration:
+        a = torch.empty(2 ** 30, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    # per-kernel totals over the timed steps
+    per = {}
+    for recs in recs_all:
+        for r in recs:
+            k = PASS_NAMES[r["type"]]
+            d = per.setdefault(k, {"seconds": 0.0, "launches": 0, "bytes": 0.0, "flops": 0.0})
+            d["seconds"] += r["seconds"]
+            d["launches"] += 1
+            d["bytes"] += r["bytes_alg"]
+            d["flops"] += r["flops"]
+    dom = max(per, key=lambda k: per[k]["seconds"])
+    d = per[dom]
+    avg_s = d["seconds"] / d["launches"]
+    bytes_launch = d["bytes"] / d["launches"]
+    flops_launch = d["flops"] / d["launches"]
+    gbs = bytes_launch / avg_s / 1e9
+    tfl = flops_launch / avg_s / 1e12
+    fpeak = MFMA_F32_PEAK_TFLOPS if prec == q.C64 else MFMA_F64_PEAK_TFLOPS
+    if tfl / fpeak > gbs / HBM_PEAK_GBS:
+        roof = {"bound": "mfma", "achieved": round(tfl, 2), "peak": fpeak, "unit": "TFLOP/s",
+                "frac": round(tfl / fpeak, 4)}
+    else:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    tr = traffic_for(dom, args.workload, bytes_launch)
+    roof["traffic"] = tr
+    roof["kernel"] = dom
+    roof["launches_per_step"] = d["launches"] // args.steps
+    roof["avg_launch_ms"] = round(avg_s * 1e3, 4)
+    roof["alg_bytes_per_launch"] = bytes_launch
+    roof["alg_flops_per_launch"] = flops_launch
+
+    step_bytes = sum(p["bytes_alg"] for p in passes) + (2 ** n) * amp
+    value = step_bytes / (ms * 1e-3) / 1e9
+    pass_time = sum(r["seconds"] for r in recs_all[-1])
+    out = {
+        "metric": "circuit wall time + HBM GB/s at 30q c64; learned vs plain plan speedup",
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == q.C64 else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": desc, "n_qubits": n, "gates": len(circ.gates),
+                   "passes": st["n_passes"], "plan": "fused"},
+        "circuit_ms": round(pass_time * 1e3, 3),
+        "plan_s": round(plan_s, 4),
+        "norm_error": abs(norm - 1.0),
+        "kernels": {k: {"ms_per_step": round(v["seconds"] / args.steps * 1e3, 3),
+                        "launches_per_step": v["launches"] // args.steps} for k, v in per.items()},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(circ, args.cpu_seconds)
+        out["cpu_baseline"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in cb.items()
+                               if k in ("value", "unit", "cores", "kind", "sample")}
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+    sim.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,296 @@
+/*
+ * qops.h -- C ABI of libqops, a full-state quantum circuit simulator for
+ * AMD Instinct MI355X (gfx950) with profile-guided gate fusion and virtual
+ * swaps.
+ *
+ * Method (paper: QOPS, profile-guided optimisation of quantum circuit
+ * simulation):
+ *   - Sec. II-B: a Schroedinger-style (full-state) simulation keeps all 2^n
+ *     complex amplitudes of an n-qubit register and updates them gate by
+ *     gate; it can report the final probability distribution.
+ *   - Sec. II-B / Fig. 4: index bits that are cheap to reach (the "chunk
+ *     segment") make gates fast; here the cheap tier is a work-group tile
+ *     held in registers and LDS, the expensive tier a strided sweep of HBM.
+ *   - Sec. III-C: a profiling run records per-gate counters (gate kind x
+ *     qubit) and a timestamped gate sequence; the results of that run are
+ *     still valid simulation results (Sec. IV-A).
+ *   - Sec. III-D: virtual swap turns a SWAP into a relabelling of where a
+ *     logical qubit lives instead of moving amplitudes; single-qubit gate
+ *     merging fuses runs of one-qubit gates into one unitary.
+ *   - Sec. IV-E: the same circuit is simulated many times with new
+ *     parameters; expectation values are read out after each run.
+ *
+ * Conventions (all calls):
+ *   - Logical qubit q is bit q of a logical basis index (qubit 0 = LSB).
+ *   - A gate on ordered qubits (q_0..q_{k-1}) has a 2^k x 2^k matrix whose
+ *     row/column index bit j belongs to q_j.  Controls are all on |1>.
+ *   - Amplitudes are interleaved (re, im): complex64 (QOPS_C64, 8 bytes) or
+ *     complex128 (QOPS_C128, 16 bytes).
+ *   - The device state is stored in PHYSICAL order: logical qubit q lives in
+ *     physical index bit l2p[q].  Readout calls map back to logical order.
+ *   - Every call returns an int32_t status (QOPS_OK = 0 or a negative code);
+ *     qops_last_error() returns a thread-local description of the last
+ *     failure.  No call throws.
+ *   - Work is enqueued on the HIP stream given at creation.  Calls marked
+ *     "blocking" synchronise that stream before returning; the others are
+ *     asynchronous with respect to the host.
+ */
+#ifndef QOPS_C_ABI_H_
+#define QOPS_C_ABI_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status ---- */
+enum qops_status {
+    QOPS_OK = 0,
+    QOPS_INVALID_ARG = -1,      /* null pointer, bad enum, bad size          */
+    QOPS_QUBIT_RANGE = -2,      /* qubit index outside [0, n)                */
+    QOPS_DUPLICATE_QUBIT = -3,  /* a qubit listed twice in one gate          */
+    QOPS_UNSUPPORTED = -4,      /* k > 6, > 4 controls, n outside [1, 34]    */
+    QOPS_OUT_OF_MEMORY = -5,    /* device or host allocation failed          */
+    QOPS_HIP_ERROR = -6,        /* a HIP runtime call failed                 */
+    QOPS_BAD_STATE = -7,        /* handle / plan / precision mismatch        */
+    QOPS_NOT_UNITARY = -8       /* opt-in unitarity check failed             */
+};
+
+/* Thread-local, NUL-terminated description of the last failing call. */
+const char* qops_last_error(void);
+/* Library version as 10000*major + 100*minor + patch. */
+int32_t qops_version(void);
+
+/* --------------------------------------------------------- gate list ---- */
+enum qops_precision { QOPS_C64 = 0, QOPS_C128 = 1 };
+
+/* Gate kinds.  Matrices (c = cos(t/2), s = sin(t/2)):
+ *   H, X, Y, Z, S=diag(1,i), SDG, T=diag(1,e^{i pi/4}), TDG, SX=sqrt(X);
+ *   RX(t)=[[c,-is],[-is,c]], RY(t)=[[c,-s],[s,c]], RZ(t)=diag(e^{-it/2},e^{it/2}),
+ *   P(l)=diag(1,e^{il}), U3(t,p,l)=[[c,-e^{il}s],[e^{ip}s,e^{i(p+l)}c]];
+ *   CX(q0 control, q1 target), CZ, CP(l) (phase e^{il} on |11>), SWAP,
+ *   RZZ(t) (e^{-it/2} when the two bits agree, e^{+it/2} otherwise);
+ *   DENSE: the 2^k x 2^k matrix given in `mat`. */
+enum qops_kind {
+    QOPS_H = 0, QOPS_X, QOPS_Y, QOPS_Z, QOPS_S, QOPS_SDG, QOPS_T, QOPS_TDG, QOPS_SX,
+    QOPS_RX, QOPS_RY, QOPS_RZ, QOPS_P, QOPS_U3,
+    QOPS_CX, QOPS_CZ, QOPS_CP, QOPS_SWAP, QOPS_RZZ,
+    QOPS_DENSE,
+    QOPS_NUM_KINDS
+};
+
+#define QOPS_MAX_K 6
+#define QOPS_MAX_CTRL 4
+#define QOPS_MAX_QUBITS 34
+
+typedef struct qops_gate {
+    uint16_t kind;        /* enum qops_kind                                   */
+    uint8_t k;            /* number of targets (must match the kind; 1..6 for
+                             DENSE)                                          */
+    uint8_t n_ctrl;       /* extra controls, 0..4 (not allowed on SWAP)       */
+    int32_t q[6];         /* targets, logical qubits                          */
+    int32_t ctrl[4];      /* controls, logical qubits                         */
+    double param[3];      /* angles in radians (RX/RY/RZ/P/CP/RZZ: param[0];
+                             U3: theta, phi, lambda)                          */
+    const double* mat;    /* DENSE only: 2^k x 2^k complex128 row-major,
+                             interleaved (re, im); read during the call and
+                             never retained                                  */
+} qops_gate;
+
+/* ------------------------------------------------------------ handle ---- */
+typedef struct qops_sim qops_sim;
+
+/* Creates a simulator of n qubits (1 <= n <= 34).  If dev_state is non-null
+ * the handle BORROWS that device buffer (bytes >= 2^n * amplitude size; the
+ * caller keeps it alive until qops_destroy); otherwise the library allocates
+ * and owns it.  `stream` is a hipStream_t (null = default stream).  The state
+ * is NOT initialised: call qops_init_basis or qops_init_amplitudes. */
+int32_t qops_create(int32_t n, int32_t precision, void* dev_state, size_t bytes, void* stream,
+                    qops_sim** out);
+/* Frees library-owned memory and plans.  Null is accepted. */
+int32_t qops_destroy(qops_sim* h);
+/* Device pointer of the state (physical order) and its size in bytes. */
+int32_t qops_state_pointer(qops_sim* h, void** dev_ptr, size_t* bytes);
+
+/* Sets |x> (x in logical order) and resets the layout to the identity. */
+int32_t qops_init_basis(qops_sim* h, uint64_t x);
+/* Copies 2^n amplitudes (precision of the handle, logical order) from host
+ * memory and resets the layout to the identity.  Blocking. */
+int32_t qops_init_amplitudes(qops_sim* h, const void* host);
+
+/* ------------------------------------------------------------- plans ---- */
+/* Plan modes:
+ *   GATEWISE  one HBM sweep per gate, no fusion (the unoptimised simulator;
+ *             the gate-by-gate baseline)
+ *   FUSED     single-qubit merging, diagonal riding and tile packing with
+ *             built-in heuristics
+ *   PROFILED  like FUSED, but every candidate plan is priced with the cost
+ *             table measured by a profiling run (opts.profile)
+ *   LEARNED   like PROFILED, priced by a trained cost model (opts.model);
+ *             falls back to PROFILED pricing when no model is given */
+enum qops_plan_mode { QOPS_PLAN_GATEWISE = 0, QOPS_PLAN_FUSED = 1, QOPS_PLAN_PROFILED = 2,
+                      QOPS_PLAN_LEARNED = 3 };
+enum qops_swap_mode { QOPS_SWAP_VIRTUAL = 0, QOPS_SWAP_PHYSICAL = 1 };
+
+typedef struct qops_profile qops_profile;
+typedef struct qops_model qops_model;
+typedef struct qops_plan qops_plan;
+
+typedef struct qops_plan_opts {
+    int32_t mode;          /* enum qops_plan_mode (default FUSED)             */
+    int32_t swap_mode;     /* enum qops_swap_mode (default VIRTUAL)           */
+    int32_t tile_upper;    /* upper tile qubits per pass beyond the 6 lane
+                              qubits; 0 = choose automatically                */
+    int32_t max_fuse_k;    /* widest dense block the planner may build by
+                              composing gates (1 = only 1q merging); 0 = auto */
+    int32_t use_mfma;      /* 1 = matrix cores for dense blocks with k >= 4
+                              (default), 0 = vector ALU only                  */
+    int32_t check_unitary; /* 1 = reject non-unitary DENSE input (1e-9)       */
+    const qops_profile* profile;  /* PROFILED / LEARNED pricing input         */
+    const qops_model* model;      /* LEARNED pricing input                    */
+} qops_plan_opts;
+
+/* Fills opts with the defaults listed above. */
+int32_t qops_plan_opts_default(qops_plan_opts* opts);
+
+/* Builds an execution plan for `gates` on an n-qubit register of the given
+ * precision, starting from layout l2p_in (null = identity).  Gates and DENSE
+ * matrices are copied; the plan is independent of any handle.  FP64 unitary
+ * composition happens here. */
+int32_t qops_plan_build(int32_t n, int32_t precision, const int32_t* l2p_in, const qops_gate* gates,
+                        size_t n_gates, const qops_plan_opts* opts, qops_plan** out);
+int32_t qops_plan_free(qops_plan* p);
+
+typedef struct qops_plan_stats {
+    int32_t n_passes;          /* kernel launches over the state              */
+    int32_t n_tile_passes;     /* of which fused tile passes                  */
+    int32_t n_permute_passes;  /* of which physical bit-permutation passes    */
+    int32_t n_ops;             /* fused operations after merging              */
+    int32_t n_gates_in;        /* gates given                                 */
+    int32_t n_virtual_swaps;   /* SWAPs turned into layout updates            */
+    int32_t tile_upper;        /* chosen upper tile width                     */
+    int32_t max_fuse_k;        /* chosen fusion width                         */
+    double bytes_alg;          /* algorithmic HBM bytes of all passes         */
+    double predicted_s;        /* cost-model prediction (0 if not priced)     */
+    double plan_seconds;       /* host time spent building the plan           */
+} qops_plan_stats;
+int32_t qops_plan_stats_get(const qops_plan* p, qops_plan_stats* out);
+/* The layout (l2p) the plan leaves behind. */
+int32_t qops_plan_final_layout(const qops_plan* p, int32_t* l2p);
+
+/* Plan introspection (host only; no GPU needed).  Lowered operations act on
+ * PHYSICAL bits after virtual swaps, single-qubit merging and diagonal
+ * fusion.  kind: 0 = one-qubit (2x2 on t[0]), 1 = diagonal table over bits
+ * t[0..k-1], 2 = dense 2^k x 2^k on t[0..k-1] (matrix bit order), 3 =
+ * physical bit exchange of t[0], t[1].  `mat` (nullable) receives the
+ * matrix (2*4^k doubles) or diagonal table (2*2^k doubles), interleaved. */
+typedef struct qops_op_info {
+    int32_t kind;
+    int32_t k;
+    int32_t t[10];
+    uint64_t cmask;        /* physical control bits                           */
+    int32_t pass;          /* index of the pass that executes the operation   */
+    int32_t n_merged;      /* input gates folded into this operation          */
+} qops_op_info;
+int32_t qops_plan_num_ops(const qops_plan* p, size_t* n);
+int32_t qops_plan_op(const qops_plan* p, size_t i, qops_op_info* info, double* mat);
+
+/* Pass types: 0 register tile, 1 LDS tile (dense blocks), 2 whole state in
+ * one work-group's LDS, 3 gate-wise HBM sweep, 4 physical bit exchange. */
+typedef struct qops_pass_info {
+    int32_t type;
+    int32_t tile_bits;     /* L: the pass touches tiles of 2^L amplitudes     */
+    int32_t n_upper;       /* upper tile bits (beyond physical bits 0..5)     */
+    int32_t upper[8];      /* those physical bits                             */
+    int32_t n_ops;         /* lowered operations in the pass                  */
+    int32_t n_remaps;      /* register/LDS remaps inside the pass             */
+    int32_t n_mfma;        /* dense blocks on matrix cores                    */
+    double bytes_alg;      /* algorithmic HBM bytes                           */
+    double flops;          /* algorithmic floating-point operations           */
+} qops_pass_info;
+int32_t qops_plan_pass_info(const qops_plan* p, size_t i, qops_pass_info* info);
+
+/* Runs a plan on the handle (n, precision and the handle's current layout
+ * must equal the plan's; otherwise QOPS_BAD_STATE).  Asynchronous. */
+int32_t qops_run_plan(qops_sim* h, const qops_plan* p);
+/* Re-binds the angles / dense matrices of a plan to a new gate list with the
+ * same structure (same kinds and qubits), re-composing fused blocks in FP64
+ * without re-planning.  For repeated runs with new parameters. */
+int32_t qops_plan_update(qops_plan* p, const qops_gate* gates, size_t n_gates);
+
+/* Plans (opts may be null = defaults) and runs a gate list.  Asynchronous. */
+int32_t qops_apply(qops_sim* h, const qops_gate* gates, size_t n_gates, const qops_plan_opts* opts);
+
+/* --------------------------------------------------------- profiling ---- */
+/* A profiling run (paper Sec. III-C) executes a plan exactly like
+ * qops_run_plan -- the state it leaves is the normal result -- while timing
+ * every pass with HIP events on the handle's stream (the context record:
+ * which pass, which operations, start/end time) and counting gates per kind
+ * and qubit (the counter record).  Blocking.  The profile is library-owned
+ * until qops_profile_free. */
+typedef struct qops_pass_record {
+    int32_t pass;          /* index in the plan                               */
+    int32_t type;          /* pass type (see qops_pass_info)                  */
+    int32_t n_ops;         /* lowered operations                              */
+    int32_t n_gates;       /* input gates folded into them                    */
+    int32_t tile_bits;
+    int32_t n_mfma;
+    int32_t max_k;
+    int32_t n_remaps;
+    double t_begin;        /* seconds since the first pass started            */
+    double seconds;        /* device time of the pass                         */
+    double bytes_alg;      /* algorithmic HBM bytes                           */
+    double flops;
+    uint64_t phys_mask;    /* physical bits targeted by the pass              */
+} qops_pass_record;
+
+int32_t qops_profile_run(qops_sim* h, const qops_plan* p, qops_profile** out);
+int32_t qops_profile_num_passes(const qops_profile* pr, size_t* n);
+int32_t qops_profile_pass(const qops_profile* pr, size_t i, qops_pass_record* rec);
+/* Gate counters: counts[kind * n + q] for logical qubit q (targets and
+ * controls), and the same per physical bit at the time of the gate. */
+int32_t qops_profile_counts(const qops_profile* pr, int32_t* logical, int32_t* physical);
+/* Sum of pass times, and the plan's qubit count. */
+int32_t qops_profile_total(const qops_profile* pr, double* seconds, int32_t* n);
+/* Cost-model features of every pass (64 floats per pass, pass order). */
+int32_t qops_profile_features(const qops_profile* pr, float* out);
+/* Writes the profile (counters, pass records) as JSON. */
+int32_t qops_profile_dump(const qops_profile* pr, const char* path);
+/* Merges the pass records of `src` into `dst` (a cost table built from many
+ * profiling runs). */
+int32_t qops_profile_merge(qops_profile* dst, const qops_profile* src);
+int32_t qops_profile_free(qops_profile* pr);
+
+/* ------------------------------------------------------------ layout ---- */
+/* SWAP of logical qubits a and b.  VIRTUAL: exchange l2p[a] and l2p[b], move
+ * no amplitude.  PHYSICAL: one bit-exchange pass over the state. */
+int32_t qops_swap(qops_sim* h, int32_t a, int32_t b, int32_t mode);
+/* Copies the logical-to-physical map (n int32). */
+int32_t qops_get_layout(qops_sim* h, int32_t* l2p);
+/* Moves amplitudes so that logical qubit q lives in physical bit l2p[q]
+ * (a permutation of 0..n-1), by bit-exchange passes. */
+int32_t qops_set_layout(qops_sim* h, const int32_t* l2p);
+
+/* ----------------------------------------------------------- readout ---- */
+enum qops_order { QOPS_ORDER_LOGICAL = 0, QOPS_ORDER_PHYSICAL = 1 };
+/* Copies the 2^n amplitudes to host memory (caller-owned, 2^n * amplitude
+ * size bytes) in logical or physical order.  Blocking. */
+int32_t qops_read_state(qops_sim* h, void* host, int32_t order);
+/* sum_x |psi_x|^2, FP64 accumulation, deterministic order.  Blocking. */
+int32_t qops_norm(qops_sim* h, double* out);
+/* Marginal distribution of logical qubits q[0..m-1] (1 <= m <= n):
+ * out[y] (2^m doubles) = sum of |psi_x|^2 over x whose bit q_j equals bit j
+ * of y.  FP64, deterministic.  Blocking. */
+int32_t qops_probabilities(qops_sim* h, const int32_t* qubits, int32_t m, double* out);
+/* <Z_q> = sum_x |psi_x|^2 (1 - 2 b_q(x)) for every logical qubit (n
+ * doubles).  FP64, deterministic.  Blocking. */
+int32_t qops_expect_z(qops_sim* h, double* out);
+/* Waits for all work enqueued on the handle's stream. */
+int32_t qops_synchronize(qops_sim* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QOPS_C_ABI_H_ */

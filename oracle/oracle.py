@@ -56,6 +56,7 @@ def lib():
         L.orc_run.argtypes = [ctypes.c_int, dp, ctypes.c_int, ip, ip, ip, ip, ip, dp, dp,
                               ctypes.POINTER(ctypes.c_int64)]
         L.orc_basis.argtypes = [ctypes.c_int, dp, ctypes.c_uint64]
+        L.orc_num_threads.restype = ctypes.c_int
         L.orc_norm.argtypes = [ctypes.c_int, dp]
         L.orc_norm.restype = ctypes.c_double
         L.orc_probabilities.argtypes = [ctypes.c_int, dp, ctypes.c_int, ip, dp]
@@ -156,6 +157,21 @@ def apply_matrix(n: int, psi: np.ndarray, u: np.ndarray, qubits: Sequence[int],
     if rc != 0:
         raise ValueError(f"oracle: apply rejected ({rc})")
     return psi
+
+
+def apply_matrix_inplace(n: int, psi: np.ndarray, u: np.ndarray, qubits: Sequence[int]) -> None:
+    """Like apply_matrix, without the copy (for large states)."""
+    assert psi.dtype == np.complex128 and psi.flags.c_contiguous
+    q = np.asarray(qubits, dtype=np.int32)
+    c = np.zeros(1, dtype=np.int32)
+    uu = np.ascontiguousarray(u.astype(np.complex128)).view(np.float64).ravel()
+    rc = lib().orc_apply_matrix(n, _dp(psi.view(np.float64)), len(q), _ip(q), 0, _ip(c), _dp(uu))
+    if rc != 0:
+        raise ValueError(f"oracle: apply rejected ({rc})")
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
 
 
 def norm(psi: np.ndarray) -> float:

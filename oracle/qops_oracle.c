@@ -211,6 +211,17 @@ int orc_run(int n, double* psi, int ngates, const int* kind, const int* nq, cons
     return 0;
 }
 
+/* Threads the OpenMP loops use. */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    extern int omp_get_max_threads(void);
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* |x0>: all zero except amplitude x0 = 1. */
 void orc_basis(int n, double* psi, uint64_t x0)
 {

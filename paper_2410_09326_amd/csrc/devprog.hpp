@@ -1,0 +1,68 @@
+// Device-side pass programs: the plain-old-data records the planner writes
+// and the kernels read.  Shared between host (planner/runtime) and device
+// (kernels) translation units of libqops.
+#pragma once
+#include <stdint.h>
+
+namespace qops {
+
+// Operation types inside a tile pass.
+enum OpType : int32_t {
+    OP_NONE = 0,
+    OP_1Q_REG = 1,    // 2x2 on a register bit          a = register bit
+    OP_1Q_LANE = 2,   // 2x2 on a lane bit (shuffles)    a = lane bit (0..5)
+    OP_DIAG = 3,      // diagonal table over m bits      a = m, pos[i] = encoded source of bit i
+    OP_REMAP = 4,     // registers -> LDS -> registers   b = new mapping
+    OP_TO_LDS = 5,    // registers -> LDS
+    OP_FROM_LDS = 6,  // LDS -> registers                b = new mapping
+    OP_DENSE_LDS = 7, // 2^k x 2^k on tile positions, vector ALU, in LDS   a = k, pos = tile positions
+    OP_MFMA = 8,      // 2^k x 2^k on tile positions, matrix cores, in LDS  a = k, pos = tile positions
+    OP_DIAG_LDS = 9   // diagonal table on tile positions, in LDS (whole-state kernel)
+};
+
+// Encoded source of one bit of a diagonal's table index (OP_DIAG pos[i]).
+enum BitSrc : int32_t { SRC_LANE = 0, SRC_WAVE = 1, SRC_REG = 2, SRC_GLOB = 3 };
+__host__ __device__ inline int32_t enc_src(int32_t cls, int32_t v) { return (cls << 8) | v; }
+
+struct DevOp {              // 64 bytes
+    int32_t type;
+    int32_t a;
+    int32_t coef;           // offset of the coefficients in the coefficient array (scalar units)
+    int32_t b;
+    uint32_t c_lane;        // controls on lane bits (tile positions 0..5)
+    uint32_t c_wave;        // controls on wave-id bits (current mapping)
+    uint32_t c_reg;         // controls on register-slot bits (current mapping)
+    uint32_t c_tile;        // controls on tile positions (LDS ops)
+    uint64_t c_glob;        // controls on physical bits outside the tile (checked per tile)
+    int32_t pos[6];
+};
+static_assert(sizeof(DevOp) == 64, "DevOp layout");
+
+#define QOPS_MAX_UP 8
+#define QOPS_MAX_QUBITS_DEV 34
+#define QOPS_MAX_RUNS 12
+
+// Header of one tile pass.  The tile holds 2^L amplitudes: tile positions
+// 0..5 are physical bits 0..5 (one per lane bit), tile position 6+u is
+// physical bit up_phys[u].  The other physical bits index the tile.
+struct PassHdr {
+    int32_t n;
+    int32_t L;
+    int32_t nup;                    // L - 6
+    int32_t nops;
+    int32_t op0;                    // first op in the op array
+    uint32_t map0;                  // mapping used for the load
+    int32_t nruns;                  // runs of non-tile physical bits
+    int32_t lds_bytes;              // dynamic LDS needed (0 if no LDS op)
+    int32_t up_phys[QOPS_MAX_UP];
+    int32_t run_start[QOPS_MAX_RUNS];  // physical start bit of each run
+    int32_t run_len[QOPS_MAX_RUNS];
+    int32_t run_gshift[QOPS_MAX_RUNS]; // bit offset of the run inside the tile number
+    int32_t pad[1];
+};
+
+// A mapping assigns the upper tile positions to register bits (first R
+// nibbles) and wave bits (next W nibbles).
+__host__ __device__ inline int32_t map_get(uint32_t m, int i) { return (int32_t)((m >> (4 * i)) & 15u); }
+
+}  // namespace qops

@@ -1,0 +1,1209 @@
+// State-vector kernels for gfx950 (CDNA4, wave64).
+//
+// Tile pass (the "chunk segment" of the paper's storage simulator, Sec. II-B,
+// mapped onto the GPU memory hierarchy): a work-group owns a tile of 2^L
+// amplitudes.  Tile positions 0..5 are physical bits 0..5 and are held one
+// per lane, so every load/store of a wave is 64 consecutive amplitudes;
+// gates on those bits use cross-lane shuffles.  The upper positions are split
+// into R register bits (gates applied in registers) and W wave bits (changed
+// by a remap through LDS).  Dense k-qubit blocks run on the LDS copy of the
+// tile, on the vector ALU or on matrix cores (MFMA, 16x16x4 f32 / f64).
+// One read and one write of the state per pass, however many gates it holds.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "devprog.hpp"
+#include "kernels.hpp"
+
+namespace qops {
+
+// Compile-time loop: calls f(std::integral_constant<int, I>) for I = 0..N-1,
+// so that every register index is a constant and the state stays in VGPRs.
+template <int I, int N, typename F>
+__device__ __forceinline__ void sfor_impl(F& f)
+{
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        sfor_impl<I + 1, N>(f);
+    }
+}
+template <int N, typename F>
+__device__ __forceinline__ void sfor(F&& f)
+{
+    sfor_impl<0, N>(f);
+}
+
+template <typename T> struct CxT;
+template <> struct CxT<float> { using V = float2; using A4 = float __attribute__((ext_vector_type(4))); };
+template <> struct CxT<double> { using V = double2; using A4 = double __attribute__((ext_vector_type(4))); };
+
+template <typename V>
+__device__ __forceinline__ V cmul(V a, V b)
+{
+    V r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+
+// m0*x0 + m1*x1 (complex)
+template <typename V>
+__device__ __forceinline__ V cdot2(V m0, V x0, V m1, V x1)
+{
+    V r;
+    r.x = m0.x * x0.x - m0.y * x0.y + m1.x * x1.x - m1.y * x1.y;
+    r.y = m0.x * x0.y + m0.y * x0.x + m1.x * x1.y + m1.y * x1.x;
+    return r;
+}
+
+// Component-wise select by value (a conditional on two struct lvalues would
+// select an address and pin the register array in scratch memory).
+template <typename V>
+__device__ __forceinline__ V csel(bool c, V a, V b)
+{
+    V r;
+    r.x = c ? a.x : b.x;
+    r.y = c ? a.y : b.y;
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ typename CxT<T>::V ldc(const T* __restrict__ c, int i)
+{
+    typename CxT<T>::V v;
+    v.x = c[2 * i];
+    v.y = c[2 * i + 1];
+    return v;
+}
+
+// Inserts a zero bit at every set position of `mask` (ascending) into g.
+__device__ __forceinline__ uint32_t spread_mask(uint32_t g, uint32_t mask)
+{
+    while (mask) {
+        const int p = __builtin_ctz(mask);
+        mask &= mask - 1;
+        const uint32_t low = g & ((1u << p) - 1u);
+        g = ((g >> p) << (p + 1)) | low;
+    }
+    return g;
+}
+
+__device__ __forceinline__ uint64_t spread_mask64(uint64_t g, uint64_t mask)
+{
+    while (mask) {
+        const int p = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        const uint64_t low = g & ((1ull << p) - 1ull);
+        g = ((g >> p) << (p + 1)) | low;
+    }
+    return g;
+}
+
+// ---------------------------------------------------------------------------
+// Register-resident operations
+// ---------------------------------------------------------------------------
+
+// 2x2 on register bit B.  Register-slot controls `creg` are compile-time per
+// slot and uniform; `tok` is the per-lane control result.
+template <int B, int R, bool CTRL, typename V>
+__device__ __forceinline__ void oneq_reg_b(V (&a)[1 << R], V m00, V m01, V m10, V m11, uint32_t creg, bool tok)
+{
+    sfor<(1 << R)>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if constexpr (!(j & (1 << B))) {
+            constexpr int j1 = j | (1 << B);
+            if (!CTRL || ((uint32_t)j & creg) == creg) {
+                const V x0 = a[j], x1 = a[j1];
+                const V y0 = cdot2(m00, x0, m01, x1);
+                const V y1 = cdot2(m10, x0, m11, x1);
+                if (CTRL) {
+                    a[j] = csel(tok, y0, x0);
+                    a[j1] = csel(tok, y1, x1);
+                } else {
+                    a[j] = y0;
+                    a[j1] = y1;
+                }
+            }
+        }
+    });
+}
+
+template <int R, bool CTRL, typename V>
+__device__ __forceinline__ void oneq_reg(int b, V (&a)[1 << R], V m00, V m01, V m10, V m11, uint32_t creg, bool tok)
+{
+    switch (b) {
+    case 0: oneq_reg_b<0, R, CTRL>(a, m00, m01, m10, m11, creg, tok); break;
+    case 1: if constexpr (R > 1) oneq_reg_b<1, R, CTRL>(a, m00, m01, m10, m11, creg, tok); break;
+    case 2: if constexpr (R > 2) oneq_reg_b<2, R, CTRL>(a, m00, m01, m10, m11, creg, tok); break;
+    case 3: if constexpr (R > 3) oneq_reg_b<3, R, CTRL>(a, m00, m01, m10, m11, creg, tok); break;
+    case 4: if constexpr (R > 4) oneq_reg_b<4, R, CTRL>(a, m00, m01, m10, m11, creg, tok); break;
+    case 5: if constexpr (R > 5) oneq_reg_b<5, R, CTRL>(a, m00, m01, m10, m11, creg, tok); break;
+    default: break;
+    }
+}
+
+// Cross-lane exchange through ds_bpermute; `addr` = 4 * (lane ^ mask).
+__device__ __forceinline__ float shfl_xor_f(float v, int addr)
+{
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+__device__ __forceinline__ double shfl_xor_f(double v, int addr)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// 2x2 on lane bit t: each lane computes its own output from its amplitude
+// and its partner's (lane ^ 2^t).
+template <int R, bool CTRL, typename V>
+__device__ __forceinline__ void oneq_lane(int t, int lane, V (&a)[1 << R], V m00, V m01, V m10, V m11,
+                                          uint32_t creg, bool tok)
+{
+    const bool hi = (lane >> t) & 1;
+    const V ms = csel(hi, m11, m00);
+    const V mo = csel(hi, m10, m01);
+    const int addr = (lane ^ (1 << t)) << 2;
+    sfor<(1 << R)>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if (!CTRL || ((uint32_t)j & creg) == creg) {
+            V p;
+            p.x = shfl_xor_f(a[j].x, addr);
+            p.y = shfl_xor_f(a[j].y, addr);
+            const V y = cdot2(ms, a[j], mo, p);
+            if (CTRL)
+                a[j] = csel(tok, y, a[j]);
+            else
+                a[j] = y;
+        }
+    });
+}
+
+// ---------------------------------------------------------------------------
+// LDS-resident operations (tile of 2^L amplitudes at `lds`)
+// ---------------------------------------------------------------------------
+
+// Dense 2^K x 2^K on tile positions pos[0..K-1] (matrix bit order), vector
+// ALU.  Every thread handles whole groups.
+template <int K, typename T>
+__device__ void dense_lds(typename CxT<T>::V* lds, int L, const DevOp& op, const T* __restrict__ U, int tid,
+                          int nthr)
+{
+    using V = typename CxT<T>::V;
+    constexpr int D = 1 << K;
+    uint32_t mask = 0;
+    uint32_t toff[D];
+#pragma unroll
+    for (int s = 0; s < D; ++s) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (s & (1 << j)) o |= 1u << op.pos[j];
+        toff[s] = o;
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) mask |= 1u << op.pos[j];
+    const uint32_t ngroups = 1u << (L - K);
+    for (uint32_t g = tid; g < ngroups; g += nthr) {
+        const uint32_t gb = spread_mask(g, mask);
+        if ((gb & op.c_tile) != op.c_tile) continue;
+        V in[D];
+#pragma unroll
+        for (int s = 0; s < D; ++s) in[s] = lds[gb + toff[s]];
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+            V acc;
+            acc.x = 0;
+            acc.y = 0;
+#pragma unroll
+            for (int s = 0; s < D; ++s) {
+                const T ur = U[2 * (r * D + s)], ui = U[2 * (r * D + s) + 1];
+                acc.x += ur * in[s].x - ui * in[s].y;
+                acc.y += ur * in[s].y + ui * in[s].x;
+            }
+            lds[gb + toff[r]] = acc;
+        }
+    }
+}
+
+template <typename T>
+__device__ void dense_lds_dispatch(typename CxT<T>::V* lds, int L, const DevOp& op, const T* __restrict__ U,
+                                   int tid, int nthr)
+{
+    switch (op.a) {
+    case 1: dense_lds<1, T>(lds, L, op, U, tid, nthr); break;
+    case 2: dense_lds<2, T>(lds, L, op, U, tid, nthr); break;
+    case 3: dense_lds<3, T>(lds, L, op, U, tid, nthr); break;
+    case 4: if constexpr (sizeof(T) == 4) dense_lds<4, T>(lds, L, op, U, tid, nthr); break;
+    default: break;
+    }
+}
+
+// Diagonal table over m = op.a bits, in LDS.  Bit i of the table index is
+// tile position v (pos[i] = enc_src(SRC_LANE, v)) or physical bit v of the
+// tile's base index (pos[i] = enc_src(SRC_GLOB, v)).
+template <typename T>
+__device__ void diag_lds(typename CxT<T>::V* lds, int L, const DevOp& op, const T* __restrict__ tab, uint64_t base,
+                         int tid, int nthr)
+{
+    const int m = op.a;
+    uint32_t iglob = 0, tmask[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        tmask[i] = 0;
+        if (i < m) {
+            const int cls = op.pos[i] >> 8, v = op.pos[i] & 255;
+            if (cls == SRC_GLOB) iglob |= (uint32_t)((base >> v) & 1ull) << i;
+            else tmask[i] = 1u << v;
+        }
+    }
+    const uint32_t N = 1u << L;
+    for (uint32_t x = tid; x < N; x += nthr) {
+        uint32_t idx = iglob;
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+            if (x & tmask[i]) idx |= 1u << i;
+        lds[x] = cmul(lds[x], ldc(tab, (int)idx));
+    }
+}
+
+// Dense 2^K x 2^K on tile positions with matrix cores.  The block is the
+// real embedding M (2^(K+1) square, rows/cols interleaved re,im) applied to
+// the tile viewed as a 2^(K+1) x 2^(L-K) real matrix (one column per group).
+// A fragments are pre-arranged by the host (rows permuted for f64 so that
+// both precisions return the same D layout): lane l, register i of the
+// result holds real row 4(l/16)+i of column l%16.  B operand: lane l holds
+// real row 4 ks + l/16 of column l%16.
+template <int K, typename T>
+__device__ void mfma_lds(typename CxT<T>::V* lds, int L, const DevOp& op, const T* __restrict__ A, int lane,
+                         int wave, int nwaves)
+{
+    using V = typename CxT<T>::V;
+    using A4 = typename CxT<T>::A4;
+    constexpr int KS = 1 << (K - 1);   // k-steps of 4 real rows
+    constexpr int RB = 1 << (K - 3);   // row blocks of 16 real rows
+    uint32_t mask = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) mask |= 1u << op.pos[j];
+    // offset of complex index s inside a group
+    auto toff = [&](uint32_t s) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (s & (1u << j)) o |= 1u << op.pos[j];
+        return o;
+    };
+    const int krow = lane >> 4;
+    const uint32_t in_lane = (krow >> 1) ? (1u << op.pos[0]) : 0u;               // s bit 0
+    const uint32_t out_lane = ((krow & 1) ? (1u << op.pos[1]) : 0u) | ((krow >> 1) ? (1u << op.pos[2]) : 0u);
+    const uint32_t ncb = 1u << (L - K - 4);
+    for (uint32_t cb = wave; cb < ncb; cb += nwaves) {
+        const uint32_t col = cb * 16 + (lane & 15);
+        const uint32_t gb = spread_mask(col, mask);
+        const bool ok = (gb & op.c_tile) == op.c_tile;
+        T bv[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const V v = lds[gb + toff((uint32_t)(2 * ks)) + in_lane];
+            bv[ks] = (krow & 1) ? v.y : v.x;
+        }
+#pragma unroll 1
+        for (int rb = 0; rb < RB; ++rb) {
+            A4 acc = {0, 0, 0, 0};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const T av = A[(rb * KS + ks) * 64 + lane];
+                if constexpr (sizeof(T) == 4)
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[ks], acc, 0, 0, 0);
+                else
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[ks], acc, 0, 0, 0);
+            }
+            if (ok) {
+                const uint32_t o0 = gb + toff((uint32_t)(8 * rb)) + out_lane;
+                V w0, w1;
+                w0.x = acc[0];
+                w0.y = acc[1];
+                w1.x = acc[2];
+                w1.y = acc[3];
+                lds[o0] = w0;
+                lds[o0 + (1u << op.pos[0])] = w1;
+            }
+        }
+    }
+}
+
+template <typename T>
+__device__ void mfma_dispatch(typename CxT<T>::V* lds, int L, const DevOp& op, const T* __restrict__ A, int lane,
+                              int wave, int nwaves)
+{
+    switch (op.a) {
+    case 3: mfma_lds<3, T>(lds, L, op, A, lane, wave, nwaves); break;
+    case 4: mfma_lds<4, T>(lds, L, op, A, lane, wave, nwaves); break;
+    case 5: mfma_lds<5, T>(lds, L, op, A, lane, wave, nwaves); break;
+    case 6: mfma_lds<6, T>(lds, L, op, A, lane, wave, nwaves); break;
+    default: break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tile pass kernel
+// ---------------------------------------------------------------------------
+
+template <int R, int W>
+struct MapState {
+    uint64_t rb[R];     // physical offset of register bit b
+    uint32_t lb[R];     // LDS offset of register bit b
+    uint64_t tphys;     // physical offset of this thread (lane + wave bits)
+    uint32_t tlds;      // LDS offset of this thread
+    uint32_t map;
+};
+
+template <int R, int W>
+__device__ __forceinline__ void set_map(MapState<R, W>& ms, uint32_t map, const int32_t* __restrict__ up_phys, int lane,
+                                        int wave)
+{
+    ms.map = map;
+    sfor<R>([&](auto bc) {
+        constexpr int b = decltype(bc)::value;
+        const int u = map_get(map, b);
+        ms.rb[b] = 1ull << up_phys[u];
+        ms.lb[b] = 1u << (6 + u);
+    });
+    uint64_t tp = (uint64_t)lane;
+    uint32_t tl = (uint32_t)lane;
+    sfor<W>([&](auto wc) {
+        constexpr int w = decltype(wc)::value;
+        const int u = map_get(map, R + w);
+        if ((wave >> w) & 1) {
+            tp |= 1ull << up_phys[u];
+            tl |= 1u << (6 + u);
+        }
+    });
+    ms.tphys = tp;
+    ms.tlds = tl;
+}
+
+template <int R, int W>
+__device__ __forceinline__ uint64_t reg_phys(const MapState<R, W>& ms, int j)
+{
+    uint64_t o = 0;
+    sfor<R>([&](auto bc) {
+        constexpr int b = decltype(bc)::value;
+        if (j & (1 << b)) o |= ms.rb[b];
+    });
+    return o;
+}
+
+template <int R, int W>
+__device__ __forceinline__ uint32_t reg_lds(const MapState<R, W>& ms, int j)
+{
+    uint32_t o = 0;
+    sfor<R>([&](auto bc) {
+        constexpr int b = decltype(bc)::value;
+        if (j & (1 << b)) o |= ms.lb[b];
+    });
+    return o;
+}
+
+template <typename T, int R, int W>
+__global__ void __launch_bounds__(64 << W)
+tile_pass_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict__ hp, const DevOp* __restrict__ ops,
+                 const T* __restrict__ coef, uint64_t ntiles)
+{
+    using V = typename CxT<T>::V;
+    constexpr int NR = 1 << R;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    V* lds = reinterpret_cast<V*>(smem_raw);
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nops = hp->nops;
+    const DevOp* __restrict__ prog = ops + hp->op0;
+    const int nruns = hp->nruns;
+    const int32_t* __restrict__ up_phys = hp->up_phys;
+
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        uint64_t base = 0;
+        for (int r = 0; r < nruns; ++r) {
+            const uint64_t field = (tile >> hp->run_gshift[r]) & ((1ull << hp->run_len[r]) - 1ull);
+            base |= field << hp->run_start[r];
+        }
+        MapState<R, W> ms;
+        set_map<R, W>(ms, (uint32_t)hp->map0, up_phys, lane, wave);
+        V a[NR];
+        {
+            const V* src = st + base + ms.tphys;
+            sfor<NR>([&](auto jc) { a[decltype(jc)::value] = src[reg_phys(ms, decltype(jc)::value)]; });
+        }
+        for (int i = 0; i < nops; ++i) {
+            const DevOp op = prog[i];
+            if ((base & op.c_glob) != op.c_glob) continue;   // tile-uniform control
+            switch (op.type) {
+            case OP_1Q_REG:
+            case OP_1Q_LANE: {
+                const T* c = coef + op.coef;
+                const V m00 = ldc(c, 0), m01 = ldc(c, 1), m10 = ldc(c, 2), m11 = ldc(c, 3);
+                const bool ctrl = (op.c_lane | op.c_wave | op.c_reg) != 0;
+                const bool tok = ((uint32_t)lane & op.c_lane) == op.c_lane && ((uint32_t)wave & op.c_wave) == op.c_wave;
+                if (op.type == OP_1Q_REG) {
+                    if (ctrl)
+                        oneq_reg<R, true>(op.a, a, m00, m01, m10, m11, op.c_reg, tok);
+                    else
+                        oneq_reg<R, false>(op.a, a, m00, m01, m10, m11, 0u, true);
+                } else {
+                    if (ctrl)
+                        oneq_lane<R, true>(op.a, lane, a, m00, m01, m10, m11, op.c_reg, tok);
+                    else
+                        oneq_lane<R, false>(op.a, lane, a, m00, m01, m10, m11, 0u, true);
+                }
+                break;
+            }
+            case OP_DIAG: {
+                const T* tab = coef + op.coef;
+                const int m = op.a;
+                uint32_t ithr = 0;
+                uint32_t rm[6];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) {
+                    rm[q] = 0;
+                    if (q < m) {
+                        const int cls = op.pos[q] >> 8, v = op.pos[q] & 255;
+                        if (cls == SRC_LANE) ithr |= (uint32_t)((lane >> v) & 1) << q;
+                        else if (cls == SRC_WAVE) ithr |= (uint32_t)((wave >> v) & 1) << q;
+                        else if (cls == SRC_GLOB) ithr |= (uint32_t)((base >> v) & 1ull) << q;
+                        else rm[q] = 1u << v;
+                    }
+                }
+                sfor<NR>([&](auto jc) {
+                    constexpr int j = decltype(jc)::value;
+                    uint32_t idx = ithr;
+#pragma unroll
+                    for (int q = 0; q < 6; ++q)
+                        if ((uint32_t)j & rm[q]) idx |= 1u << q;
+                    a[j] = cmul(a[j], ldc(tab, (int)idx));
+                });
+                break;
+            }
+            case OP_REMAP:
+            case OP_TO_LDS: {
+                __syncthreads();
+                sfor<NR>([&](auto jc) { lds[ms.tlds + reg_lds(ms, decltype(jc)::value)] = a[decltype(jc)::value]; });
+                __syncthreads();
+                if (op.type == OP_REMAP) {
+                    set_map<R, W>(ms, (uint32_t)op.b, up_phys, lane, wave);
+                    sfor<NR>([&](auto jc) { a[decltype(jc)::value] = lds[ms.tlds + reg_lds(ms, decltype(jc)::value)]; });
+                }
+                break;
+            }
+            case OP_FROM_LDS: {
+                set_map<R, W>(ms, (uint32_t)op.b, up_phys, lane, wave);
+                sfor<NR>([&](auto jc) { a[decltype(jc)::value] = lds[ms.tlds + reg_lds(ms, decltype(jc)::value)]; });
+                break;
+            }
+            default:
+                break;
+            }
+        }
+        {
+            V* dst = st + base + ms.tphys;
+            sfor<NR>([&](auto jc) { dst[reg_phys(ms, decltype(jc)::value)] = a[decltype(jc)::value]; });
+        }
+    }
+}
+
+#define QOPS_TILE_VARIANTS(X) \
+    X(4, 0) X(4, 1) X(4, 2) X(5, 0) X(5, 1) X(5, 2)
+
+bool tile_variant_supported(int prec, int R, int W)
+{
+#define QOPS_CHECK(r, w) if (R == r && W == w) return true;
+    (void)prec;
+    QOPS_TILE_VARIANTS(QOPS_CHECK)
+#undef QOPS_CHECK
+    return false;
+}
+
+int tile_max_lds_bytes() { return 160 * 1024; }
+
+template <typename T, int R, int W>
+static hipError_t launch_tile_t(void* state, const PassHdr* hdr, const DevOp* ops, const void* coef, uint64_t ntiles,
+                                int lds_bytes, int grid_cap, hipStream_t s)
+{
+    using V = typename CxT<T>::V;
+    auto fn = tile_pass_kernel<T, R, W>;
+    static bool attr_done = false;
+    if (!attr_done) {
+        (void)hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, tile_max_lds_bytes());
+        attr_done = true;
+    }
+    uint64_t grid = ntiles;
+    if (grid_cap > 0 && grid > (uint64_t)grid_cap) grid = (uint64_t)grid_cap;
+    if (grid > 0x7fffffffull) grid = 0x7fffffffull;
+    hipLaunchKernelGGL(fn, dim3((unsigned)grid), dim3(64 << W), lds_bytes, s, reinterpret_cast<V*>(state), hdr, ops,
+                       reinterpret_cast<const T*>(coef), ntiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_pass(int prec, int R, int W, void* state, const PassHdr* hdr, const DevOp* ops,
+                            const void* coef, uint64_t ntiles, int lds_bytes, int grid_cap, hipStream_t s)
+{
+#define QOPS_LAUNCH(r, w)                                                                              \
+    if (R == r && W == w)                                                                              \
+        return prec == 0 ? launch_tile_t<float, r, w>(state, hdr, ops, coef, ntiles, lds_bytes, grid_cap, s) \
+                         : launch_tile_t<double, r, w>(state, hdr, ops, coef, ntiles, lds_bytes, grid_cap, s);
+    QOPS_TILE_VARIANTS(QOPS_LAUNCH)
+#undef QOPS_LAUNCH
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// LDS tile pass: the tile (2^L amplitudes, L = 6 + nup) lives in LDS and every
+// operation (dense blocks on the vector ALU or matrix cores, diagonals) works
+// on it there.  Used for passes that hold dense multi-qubit blocks.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+tile_lds_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict__ hp, const DevOp* __restrict__ ops,
+                const T* __restrict__ coef, uint64_t ntiles)
+{
+    using V = typename CxT<T>::V;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    V* lds = reinterpret_cast<V*>(smem_raw);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int L = hp->L;
+    const int nup = hp->nup;
+    const int nops = hp->nops;
+    const DevOp* __restrict__ prog = ops + hp->op0;
+    const uint32_t N = 1u << L;
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        uint64_t base = 0;
+        for (int r = 0; r < hp->nruns; ++r) {
+            const uint64_t field = (tile >> hp->run_gshift[r]) & ((1ull << hp->run_len[r]) - 1ull);
+            base |= field << hp->run_start[r];
+        }
+        // tile element e: low 6 bits = physical bits 0..5, bit 6+u = up_phys[u]
+        for (uint32_t e = tid; e < N; e += 256) {
+            uint64_t p = base + (e & 63u);
+            for (int u = 0; u < nup; ++u)
+                if ((e >> (6 + u)) & 1u) p |= 1ull << hp->up_phys[u];
+            lds[e] = st[p];
+        }
+        __syncthreads();
+        for (int i = 0; i < nops; ++i) {
+            const DevOp op = prog[i];
+            if ((base & op.c_glob) != op.c_glob) continue;
+            if (op.type == OP_DENSE_LDS)
+                dense_lds_dispatch<T>(lds, L, op, coef + op.coef, tid, 256);
+            else if (op.type == OP_MFMA)
+                mfma_dispatch<T>(lds, L, op, coef + op.coef, lane, wave, 4);
+            else if (op.type == OP_DIAG_LDS)
+                diag_lds<T>(lds, L, op, coef + op.coef, base, tid, 256);
+            __syncthreads();
+        }
+        for (uint32_t e = tid; e < N; e += 256) {
+            uint64_t p = base + (e & 63u);
+            for (int u = 0; u < nup; ++u)
+                if ((e >> (6 + u)) & 1u) p |= 1ull << hp->up_phys[u];
+            st[p] = lds[e];
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_tile_lds(int prec, void* state, const PassHdr* hdr, const DevOp* ops, const void* coef,
+                           uint64_t ntiles, int L, int grid_cap, hipStream_t s)
+{
+    const size_t bytes = (size_t(1) << L) * (prec == 0 ? 8 : 16);
+    uint64_t grid = ntiles;
+    if (grid_cap > 0 && grid > (uint64_t)grid_cap) grid = (uint64_t)grid_cap;
+    if (prec == 0) {
+        static bool done = false;
+        if (!done) {
+            (void)hipFuncSetAttribute((const void*)tile_lds_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      tile_max_lds_bytes());
+            done = true;
+        }
+        hipLaunchKernelGGL(tile_lds_kernel<float>, dim3((unsigned)grid), dim3(256), bytes, s,
+                           reinterpret_cast<float2*>(state), hdr, ops, reinterpret_cast<const float*>(coef), ntiles);
+    } else {
+        static bool done = false;
+        if (!done) {
+            (void)hipFuncSetAttribute((const void*)tile_lds_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      tile_max_lds_bytes());
+            done = true;
+        }
+        hipLaunchKernelGGL(tile_lds_kernel<double>, dim3((unsigned)grid), dim3(256), bytes, s,
+                           reinterpret_cast<double2*>(state), hdr, ops, reinterpret_cast<const double*>(coef), ntiles);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Whole state in one work-group's LDS
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__device__ void run_ops_lds(typename CxT<T>::V* lds, int n, const DevOp* __restrict__ ops, int nops,
+                           const T* __restrict__ coef, int tid, int nthr)
+{
+    const int lane = tid & 63, wave = tid >> 6;
+    for (int i = 0; i < nops; ++i) {
+        const DevOp op = ops[i];
+        if (op.type == OP_DENSE_LDS)
+            dense_lds_dispatch<T>(lds, n, op, coef + op.coef, tid, nthr);
+        else if (op.type == OP_MFMA)
+            mfma_dispatch<T>(lds, n, op, coef + op.coef, lane, wave, nthr / 64);
+        else if (op.type == OP_DIAG_LDS)
+            diag_lds<T>(lds, n, op, coef + op.coef, 0ull, tid, nthr);
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+state_lds_kernel(typename CxT<T>::V* __restrict__ st, int n, const DevOp* __restrict__ ops, int nops,
+                 const T* __restrict__ coef)
+{
+    using V = typename CxT<T>::V;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    V* lds = reinterpret_cast<V*>(smem_raw);
+    const uint32_t N = 1u << n;
+    for (uint32_t x = threadIdx.x; x < N; x += blockDim.x) lds[x] = st[x];
+    __syncthreads();
+    run_ops_lds<T>(lds, n, ops, nops, coef, threadIdx.x, blockDim.x);
+    for (uint32_t x = threadIdx.x; x < N; x += blockDim.x) st[x] = lds[x];
+}
+
+hipError_t launch_state_lds(int prec, void* state, int n, const DevOp* ops, int nops, const void* coef,
+                            hipStream_t s)
+{
+    const size_t bytes = (size_t(1) << n) * (prec == 0 ? 8 : 16);
+    if (prec == 0) {
+        static bool done = false;
+        if (!done) {
+            (void)hipFuncSetAttribute((const void*)state_lds_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                tile_max_lds_bytes());
+            done = true;
+        }
+        hipLaunchKernelGGL(state_lds_kernel<float>, dim3(1), dim3(256), bytes, s, reinterpret_cast<float2*>(state), n,
+                           ops, nops, reinterpret_cast<const float*>(coef));
+    } else {
+        static bool done = false;
+        if (!done) {
+            (void)hipFuncSetAttribute((const void*)state_lds_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                tile_max_lds_bytes());
+            done = true;
+        }
+        hipLaunchKernelGGL(state_lds_kernel<double>, dim3(1), dim3(256), bytes, s, reinterpret_cast<double2*>(state),
+                           n, ops, nops, reinterpret_cast<const double*>(coef));
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Gate-wise HBM sweep (one operation per launch; the unfused simulator)
+// ---------------------------------------------------------------------------
+
+template <typename T, int K>
+__global__ void __launch_bounds__(256)
+sweep_dense_kernel(typename CxT<T>::V* __restrict__ st, uint64_t ngroups, uint64_t tmask, uint64_t cmask,
+                   int4 p03, int2 p45, const T* __restrict__ U)
+{
+    using V = typename CxT<T>::V;
+    constexpr int D = 1 << K;
+    const int pos[6] = {p03.x, p03.y, p03.z, p03.w, p45.x, p45.y};
+    uint64_t toff[D];
+#pragma unroll
+    for (int s = 0; s < D; ++s) {
+        uint64_t o = 0;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (s & (1 << j)) o |= 1ull << pos[j];
+        toff[s] = o;
+    }
+    for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < ngroups;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t x = spread_mask64(g, tmask);
+        if ((x & cmask) != cmask) continue;
+        V in[D];
+#pragma unroll
+        for (int s = 0; s < D; ++s) in[s] = st[x + toff[s]];
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+            V acc;
+            acc.x = 0;
+            acc.y = 0;
+#pragma unroll
+            for (int s = 0; s < D; ++s) {
+                const T ur = U[2 * (r * D + s)], ui = U[2 * (r * D + s) + 1];
+                acc.x += ur * in[s].x - ui * in[s].y;
+                acc.y += ur * in[s].y + ui * in[s].x;
+            }
+            st[x + toff[r]] = acc;
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+sweep_diag_kernel(typename CxT<T>::V* __restrict__ st, uint64_t N, int m, int4 p03, int2 p45, const T* __restrict__ tab)
+{
+    const int pos[6] = {p03.x, p03.y, p03.z, p03.w, p45.x, p45.y};
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < N; x += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t idx = 0;
+        for (int i = 0; i < m; ++i) idx |= (uint32_t)((x >> pos[i]) & 1ull) << i;
+        st[x] = cmul(st[x], ldc(tab, (int)idx));
+    }
+}
+
+static unsigned grid_for(uint64_t work, unsigned block)
+{
+    uint64_t g = (work + block - 1) / block;
+    const uint64_t cap = 256ull * 64;   // enough waves to fill 256 CUs, grid-stride beyond
+    if (g > cap) g = cap;
+    if (g == 0) g = 1;
+    return (unsigned)g;
+}
+
+template <typename T>
+static hipError_t launch_sweep_t(void* state, int n, const DevOp* op, const void* coef, hipStream_t s)
+{
+    using V = typename CxT<T>::V;
+    V* st = reinterpret_cast<V*>(state);
+    const T* c = reinterpret_cast<const T*>(coef) + op->coef;
+    const int4 p03 = make_int4(op->pos[0], op->pos[1], op->pos[2], op->pos[3]);
+    const int2 p45 = make_int2(op->pos[4], op->pos[5]);
+    if (op->type == OP_DIAG_LDS) {
+        const uint64_t N = 1ull << n;
+        hipLaunchKernelGGL(sweep_diag_kernel<T>, dim3(grid_for(N, 256)), dim3(256), 0, s, st, N, op->a, p03, p45, c);
+        return hipGetLastError();
+    }
+    const int k = op->a;
+    uint64_t tmask = 0;
+    for (int j = 0; j < k; ++j) tmask |= 1ull << op->pos[j];
+    const uint64_t cmask = op->c_glob;
+    const uint64_t ng = 1ull << (n - k);
+    const dim3 grid(grid_for(ng, 256)), blk(256);
+    switch (k) {
+    case 1: hipLaunchKernelGGL((sweep_dense_kernel<T, 1>), grid, blk, 0, s, st, ng, tmask, cmask, p03, p45, c); break;
+    case 2: hipLaunchKernelGGL((sweep_dense_kernel<T, 2>), grid, blk, 0, s, st, ng, tmask, cmask, p03, p45, c); break;
+    case 3: hipLaunchKernelGGL((sweep_dense_kernel<T, 3>), grid, blk, 0, s, st, ng, tmask, cmask, p03, p45, c); break;
+    case 4: hipLaunchKernelGGL((sweep_dense_kernel<T, 4>), grid, blk, 0, s, st, ng, tmask, cmask, p03, p45, c); break;
+    case 5: hipLaunchKernelGGL((sweep_dense_kernel<T, 5>), grid, blk, 0, s, st, ng, tmask, cmask, p03, p45, c); break;
+    case 6: hipLaunchKernelGGL((sweep_dense_kernel<T, 6>), grid, blk, 0, s, st, ng, tmask, cmask, p03, p45, c); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep(int prec, void* state, int n, const DevOp* op_host, const void* coef_dev, hipStream_t s)
+{
+    return prec == 0 ? launch_sweep_t<float>(state, n, op_host, coef_dev, s)
+                     : launch_sweep_t<double>(state, n, op_host, coef_dev, s);
+}
+
+// ---------------------------------------------------------------------------
+// Bit exchange (physical SWAP) and basis initialisation
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+swap_bits_kernel(typename CxT<T>::V* __restrict__ st, uint64_t ng, uint64_t mask2, uint64_t ma, uint64_t mb)
+{
+    for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < ng; g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t x0 = spread_mask64(g, mask2) | ma;   // bit a = 1, bit b = 0
+        const uint64_t x1 = x0 ^ ma ^ mb;                  // bit a = 0, bit b = 1
+        const auto v0 = st[x0];
+        const auto v1 = st[x1];
+        st[x0] = v1;
+        st[x1] = v0;
+    }
+}
+
+hipError_t launch_swap_bits(int prec, void* state, int n, int a, int b, hipStream_t s)
+{
+    const uint64_t ng = 1ull << (n - 2);
+    const uint64_t ma = 1ull << a, mb = 1ull << b;
+    if (prec == 0)
+        hipLaunchKernelGGL(swap_bits_kernel<float>, dim3(grid_for(ng, 256)), dim3(256), 0, s,
+                           reinterpret_cast<float2*>(state), ng, ma | mb, ma, mb);
+    else
+        hipLaunchKernelGGL(swap_bits_kernel<double>, dim3(grid_for(ng, 256)), dim3(256), 0, s,
+                           reinterpret_cast<double2*>(state), ng, ma | mb, ma, mb);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) init_basis_kernel(typename CxT<T>::V* __restrict__ st, uint64_t N, uint64_t x0)
+{
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < N; x += (uint64_t)gridDim.x * blockDim.x) {
+        typename CxT<T>::V v;
+        v.x = (x == x0) ? (T)1 : (T)0;
+        v.y = 0;
+        st[x] = v;
+    }
+}
+
+hipError_t launch_init_basis(int prec, void* state, int n, uint64_t x, hipStream_t s)
+{
+    const uint64_t N = 1ull << n;
+    if (prec == 0)
+        hipLaunchKernelGGL(init_basis_kernel<float>, dim3(grid_for(N, 256)), dim3(256), 0, s,
+                           reinterpret_cast<float2*>(state), N, x);
+    else
+        hipLaunchKernelGGL(init_basis_kernel<double>, dim3(grid_for(N, 256)), dim3(256), 0, s,
+                           reinterpret_cast<double2*>(state), N, x);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// FP64 reductions (fixed order, so results are bitwise reproducible)
+// ---------------------------------------------------------------------------
+
+template <typename V>
+__device__ __forceinline__ double prob(V v)
+{
+    const double re = (double)v.x, im = (double)v.y;
+    return re * re + im * im;
+}
+
+// Tree sum over the 256 threads of a block, fixed order.  `sh` has 256 doubles.
+__device__ __forceinline__ double block_sum_256(double v, double* sh)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// Block b sums the chunk [b 2^s, (b+1) 2^s): part[b*(n+1) + 0] = sum p,
+// part[b*(n+1) + 1 + q] = sum p * bit_q(x).
+template <typename T>
+__global__ void __launch_bounds__(256)
+zsum_part_kernel(const typename CxT<T>::V* __restrict__ st, int n, int s, double* __restrict__ part)
+{
+    __shared__ double sh[256];
+    const uint64_t base = (uint64_t)blockIdx.x << s;
+    const uint32_t chunk = 1u << s;
+    const int t = threadIdx.x;
+    const int jb = s > 8 ? s - 8 : 0;           // bits 8..s-1 come from the loop counter
+    double tot = 0.0;
+    double sb[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sb[q] = 0.0;
+    for (uint32_t j = 0; (j << 8) < chunk; ++j) {
+        const uint32_t off = (j << 8) + t;
+        if (off >= chunk) break;
+        const double p = prob(st[base + off]);
+        tot += p;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (q < jb && ((j >> q) & 1u)) sb[q] += p;
+    }
+    double* out = part + (uint64_t)blockIdx.x * (n + 1);
+    const double all = block_sum_256(tot, sh);
+    if (t == 0) out[0] = all;
+    for (int q = 0; q < n; ++q) {
+        double v;
+        if (q < 8 && q < s)
+            v = block_sum_256(((t >> q) & 1) ? tot : 0.0, sh);
+        else if (q < s) {
+            double mine = 0.0;
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+                if (r == q - 8) mine = sb[r];
+            v = block_sum_256(mine, sh);
+        }
+        else
+            v = ((base >> q) & 1ull) ? all : 0.0;
+        if (t == 0) out[1 + q] = v;
+    }
+}
+
+// One block per output quantity: sums part[b*(n+1) + qi] over blocks b.
+__global__ void __launch_bounds__(256) zsum_final_kernel(const double* __restrict__ part, int nparts, int n,
+                                                         double* __restrict__ out)
+{
+    __shared__ double sh[256];
+    const int qi = blockIdx.x;
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += 256) v += part[(uint64_t)b * (n + 1) + qi];
+    const double r = block_sum_256(v, sh);
+    if (threadIdx.x == 0) out[qi] = r;
+}
+
+static int zsum_chunk_bits(int n) { return n < 16 ? n : 16; }
+
+size_t zsum_scratch_doubles(int n)
+{
+    const int s = zsum_chunk_bits(n);
+    return (size_t(1) << (n - s)) * (n + 1);
+}
+
+hipError_t launch_zsum(int prec, const void* state, int n, double* scratch, double* out, hipStream_t st)
+{
+    const int s = zsum_chunk_bits(n);
+    const unsigned nb = 1u << (n - s);
+    if (prec == 0)
+        hipLaunchKernelGGL(zsum_part_kernel<float>, dim3(nb), dim3(256), 0, st,
+                           reinterpret_cast<const float2*>(state), n, s, scratch);
+    else
+        hipLaunchKernelGGL(zsum_part_kernel<double>, dim3(nb), dim3(256), 0, st,
+                           reinterpret_cast<const double2*>(state), n, s, scratch);
+    hipLaunchKernelGGL(zsum_final_kernel, dim3(n + 1), dim3(256), 0, st, scratch, (int)nb, n, out);
+    return hipGetLastError();
+}
+
+// Marginal probabilities.  Three paths:
+//  (a) m == n: a permutation of |psi|^2, no reduction;
+//  (b) at most 12 marginal bits: block b owns the chunk [b 2^s, (b+1) 2^s),
+//      reduces it sub-chunk by sub-chunk (4096 amplitudes) in LDS with a
+//      fixed summation order, and writes 2^(marginal bits below s) partials;
+//      a second kernel sums the partials over blocks in block order;
+//  (c) otherwise one thread per output y sums its 2^(n-m) terms in order.
+struct ProbGeom {
+    int s;          // chunk bits
+    int m_lo;       // marginal bits below s
+    int m12;        // marginal bits below 12
+    uint32_t lo_mask;  // physical mask of marginal bits below s
+};
+
+static ProbGeom prob_geom(int n, int m, const int* pos)
+{
+    ProbGeom g;
+    g.s = n < 20 ? n : 20;
+    g.m_lo = 0;
+    g.m12 = 0;
+    g.lo_mask = 0;
+    for (int j = 0; j < m; ++j) {
+        if (pos[j] < g.s) {
+            g.m_lo++;
+            g.lo_mask |= 1u << pos[j];
+        }
+        if (pos[j] < 12) g.m12++;
+    }
+    return g;
+}
+
+struct PosArr {
+    int p[QOPS_MAX_QUBITS_DEV];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+probs_direct_kernel(const typename CxT<T>::V* __restrict__ st, int n, PosArr pa, double* __restrict__ out)
+{
+    const uint64_t N = 1ull << n;
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < N; x += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t y = 0;
+        for (int j = 0; j < n; ++j) y |= ((x >> pa.p[j]) & 1ull) << j;
+        out[y] = prob(st[x]);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+probs_slow_kernel(const typename CxT<T>::V* __restrict__ st, int n, int m, PosArr pa, uint64_t pmask,
+                  double* __restrict__ out)
+{
+    const uint64_t ny = 1ull << m;
+    const uint64_t nz = 1ull << (n - m);
+    for (uint64_t y = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; y < ny; y += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t xy = 0;
+        for (int j = 0; j < m; ++j) xy |= ((y >> j) & 1ull) << pa.p[j];
+        double acc = 0.0;
+        for (uint64_t z = 0; z < nz; ++z) acc += prob(st[xy | spread_mask64(z, pmask)]);
+        out[y] = acc;
+    }
+}
+
+// y index of x restricted to the marginal bits selected by `sel` (a subset of
+// the m marginal bits, in j order), compressed.
+__device__ __forceinline__ uint32_t compress_sel(uint64_t x, const PosArr& pa, int m, uint32_t sel)
+{
+    uint32_t y = 0;
+    int o = 0;
+    for (int j = 0; j < m; ++j)
+        if (sel & (1u << j)) {
+            y |= (uint32_t)((x >> pa.p[j]) & 1ull) << o;
+            ++o;
+        }
+    return y;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+probs_part_kernel(const typename CxT<T>::V* __restrict__ st, int n, int m, PosArr pa, int s, int m_lo,
+                  uint32_t sel_lo, uint32_t sel12, int m12, uint32_t mask12, double* __restrict__ part)
+{
+    __shared__ double tab[4096];
+    __shared__ double acc[4096];
+    const int t = threadIdx.x;
+    const uint64_t base = (uint64_t)blockIdx.x << s;
+    const uint32_t nacc = 1u << m_lo;
+    for (uint32_t i = t; i < nacc; i += 256) acc[i] = 0.0;
+    const int sub_bits = s < 12 ? s : 12;
+    const uint32_t sub = 1u << sub_bits;
+    const uint32_t nsub = 1u << (s - sub_bits);
+    const uint32_t n12 = 1u << m12;
+    const uint32_t nz = 1u << (sub_bits - m12);
+    __syncthreads();
+    for (uint32_t c = 0; c < nsub; ++c) {
+        const uint64_t sb = base + (uint64_t)c * sub;
+        for (uint32_t i = t; i < sub; i += 256) tab[i] = prob(st[sb + i]);
+        __syncthreads();
+        for (uint32_t y12 = t; y12 < n12; y12 += 256) {
+            // scatter y12 into the marginal bits below 12 (j order)
+            uint32_t xy = 0;
+            int o = 0;
+            for (int j = 0; j < m; ++j)
+                if (sel12 & (1u << j)) {
+                    xy |= ((y12 >> o) & 1u) << pa.p[j];
+                    ++o;
+                }
+            double v = 0.0;
+            for (uint32_t z = 0; z < nz; ++z) v += tab[xy | spread_mask(z, mask12)];
+            const uint32_t slot = compress_sel(sb | xy, pa, m, sel_lo);
+            acc[slot] += v;
+        }
+        __syncthreads();
+    }
+    for (uint32_t i = t; i < nacc; i += 256) part[(uint64_t)blockIdx.x * nacc + i] = acc[i];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+probs_reduce_kernel(const double* __restrict__ part, int n, int m, PosArr pa, int s, int m_lo, uint32_t sel_lo,
+                    uint64_t hi_mask_blocks, double* __restrict__ out)
+{
+    // hi_mask_blocks: bits of the block number that are marginal bits
+    const uint32_t ny = 1u << m;
+    const uint32_t nacc = 1u << m_lo;
+    const int nbb = n - s;
+    const uint64_t nfree = 1ull << (nbb - __popcll(hi_mask_blocks));
+    for (uint32_t y = blockIdx.x * blockDim.x + threadIdx.x; y < ny; y += gridDim.x * blockDim.x) {
+        uint32_t ylo = 0, o = 0;
+        uint64_t bfix = 0;
+        for (int j = 0; j < m; ++j) {
+            const uint32_t bit = (y >> j) & 1u;
+            if (sel_lo & (1u << j)) {
+                ylo |= bit << o;
+                ++o;
+            } else {
+                bfix |= (uint64_t)bit << (pa.p[j] - s);
+            }
+        }
+        double v = 0.0;
+        for (uint64_t f = 0; f < nfree; ++f) {
+            const uint64_t b = bfix | spread_mask64(f, hi_mask_blocks);
+            v += part[b * nacc + ylo];
+        }
+        out[y] = v;
+    }
+}
+
+size_t probs_scratch_doubles(int n, int m, const int* pos)
+{
+    if (m == n) return 0;
+    int m12 = 0;
+    for (int j = 0; j < m; ++j) m12 += pos[j] < 12 ? 1 : 0;
+    if (m > 12) return 0;
+    const ProbGeom g = prob_geom(n, m, pos);
+    return (size_t(1) << (n - g.s)) * (size_t(1) << g.m_lo);
+}
+
+hipError_t launch_probs(int prec, const void* state, int n, int m, const int* pos, double* scratch, double* out,
+                        hipStream_t st)
+{
+    PosArr pa;
+    for (int j = 0; j < QOPS_MAX_QUBITS_DEV; ++j) pa.p[j] = j < m ? pos[j] : 0;
+    uint64_t pmask = 0;
+    for (int j = 0; j < m; ++j) pmask |= 1ull << pos[j];
+    if (m == n) {
+        const uint64_t N = 1ull << n;
+        if (prec == 0)
+            hipLaunchKernelGGL(probs_direct_kernel<float>, dim3(grid_for(N, 256)), dim3(256), 0, st,
+                               reinterpret_cast<const float2*>(state), n, pa, out);
+        else
+            hipLaunchKernelGGL(probs_direct_kernel<double>, dim3(grid_for(N, 256)), dim3(256), 0, st,
+                               reinterpret_cast<const double2*>(state), n, pa, out);
+        return hipGetLastError();
+    }
+    if (m > 12) {
+        const uint64_t ny = 1ull << m;
+        if (prec == 0)
+            hipLaunchKernelGGL(probs_slow_kernel<float>, dim3(grid_for(ny, 256)), dim3(256), 0, st,
+                               reinterpret_cast<const float2*>(state), n, m, pa, pmask, out);
+        else
+            hipLaunchKernelGGL(probs_slow_kernel<double>, dim3(grid_for(ny, 256)), dim3(256), 0, st,
+                               reinterpret_cast<const double2*>(state), n, m, pa, pmask, out);
+        return hipGetLastError();
+    }
+    const ProbGeom g = prob_geom(n, m, pos);
+    uint32_t sel_lo = 0, sel12 = 0, mask12 = 0;
+    uint64_t hi_blocks = 0;
+    for (int j = 0; j < m; ++j) {
+        if (pos[j] < g.s) sel_lo |= 1u << j;
+        else hi_blocks |= 1ull << (pos[j] - g.s);
+        if (pos[j] < 12 && pos[j] < g.s) {
+            sel12 |= 1u << j;
+            mask12 |= 1u << pos[j];
+        }
+    }
+    int m12 = __builtin_popcount(sel12);
+    const unsigned nb = 1u << (n - g.s);
+    if (prec == 0)
+        hipLaunchKernelGGL(probs_part_kernel<float>, dim3(nb), dim3(256), 0, st, reinterpret_cast<const float2*>(state),
+                           n, m, pa, g.s, g.m_lo, sel_lo, sel12, m12, mask12, scratch);
+    else
+        hipLaunchKernelGGL(probs_part_kernel<double>, dim3(nb), dim3(256), 0, st,
+                           reinterpret_cast<const double2*>(state), n, m, pa, g.s, g.m_lo, sel_lo, sel12, m12, mask12,
+                           scratch);
+    const uint64_t ny = 1ull << m;
+    hipLaunchKernelGGL(probs_reduce_kernel<float>, dim3(grid_for(ny, 256)), dim3(256), 0, st, scratch, n, m, pa, g.s,
+                       g.m_lo, sel_lo, hi_blocks, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Logical-order gather (readout through the layout map)
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+gather_logical_kernel(const typename CxT<T>::V* __restrict__ st, int n, PosArr l2p, uint64_t x0, uint64_t count,
+                      typename CxT<T>::V* __restrict__ dst)
+{
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t x = x0 + i;
+        uint64_t p = 0;
+        for (int q = 0; q < n; ++q) p |= ((x >> q) & 1ull) << l2p.p[q];
+        dst[i] = st[p];
+    }
+}
+
+hipError_t launch_gather_logical(int prec, const void* state, int n, const int* l2p, uint64_t x0, uint64_t count,
+                                 void* dst, hipStream_t s)
+{
+    PosArr pa;
+    for (int j = 0; j < QOPS_MAX_QUBITS_DEV; ++j) pa.p[j] = j < n ? l2p[j] : 0;
+    if (prec == 0)
+        hipLaunchKernelGGL(gather_logical_kernel<float>, dim3(grid_for(count, 256)), dim3(256), 0, s,
+                           reinterpret_cast<const float2*>(state), n, pa, x0, count, reinterpret_cast<float2*>(dst));
+    else
+        hipLaunchKernelGGL(gather_logical_kernel<double>, dim3(grid_for(count, 256)), dim3(256), 0, s,
+                           reinterpret_cast<const double2*>(state), n, pa, x0, count, reinterpret_cast<double2*>(dst));
+    return hipGetLastError();
+}
+
+}  // namespace qops

