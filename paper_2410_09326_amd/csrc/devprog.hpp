@@ -17,8 +17,12 @@ enum OpType : int32_t {
     OP_FROM_LDS = 6,  // LDS -> registers                b = new mapping
     OP_DENSE_LDS = 7, // 2^k x 2^k on tile positions, vector ALU, in LDS   a = k, pos = tile positions
     OP_MFMA = 8,      // 2^k x 2^k on tile positions, matrix cores, in LDS  a = k, pos = tile positions
-    OP_DIAG_LDS = 9   // diagonal table on tile positions, in LDS (whole-state kernel)
+    OP_DIAG_LDS = 9,  // diagonal table on tile positions, in LDS (whole-state kernel)
+    OP_CPHASE = 10    // phase coef on amplitudes whose masked bits are all 1   b = 1: phase is -1
 };
+// OP_1Q_REG / OP_1Q_LANE: b = 1 marks an exact X (pure exchange, no arithmetic).
+// OP_MFMA / OP_DIAG_LDS in an LDS tile pass: b = 1 means `coef` is an offset
+// into the coefficients staged in LDS, b = 0 an offset into global memory.
 
 // Encoded source of one bit of a diagonal's table index (OP_DIAG pos[i]).
 enum BitSrc : int32_t { SRC_LANE = 0, SRC_WAVE = 1, SRC_REG = 2, SRC_GLOB = 3 };
@@ -54,6 +58,8 @@ struct PassHdr {
     uint32_t map0;                  // mapping used for the load
     int32_t nruns;                  // runs of non-tile physical bits
     int32_t lds_bytes;              // dynamic LDS needed (0 if no LDS op)
+    int32_t coef_src;               // LDS tile pass: coefficients staged into LDS once per
+    int32_t coef_n;                 //   work-group: coef[coef_src .. coef_src + coef_n)
     int32_t up_phys[QOPS_MAX_UP];
     int32_t run_start[QOPS_MAX_RUNS];  // physical start bit of each run
     int32_t run_len[QOPS_MAX_RUNS];

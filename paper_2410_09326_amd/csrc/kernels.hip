@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "devprog.hpp"
@@ -78,6 +79,13 @@ __device__ __forceinline__ typename CxT<T>::V ldc(const T* __restrict__ c, int i
     return v;
 }
 
+// LDS slot of tile element e: the low five bits (32 amplitudes = one row of
+// the 64 four-byte banks for complex64) are XORed with the next five, so
+// that strided groups and matrix-core column sets spread over the banks.
+// A bijection on [0, 2^L) for every L >= 5.
+// GF(2)-linear: swz(a ^ b) = swz(a) ^ swz(b).
+__host__ __device__ constexpr uint32_t swz(uint32_t e) { return e ^ ((e >> 5) & 31u); }
+
 // Inserts a zero bit at every set position of `mask` (ascending) into g.
 __device__ __forceinline__ uint32_t spread_mask(uint32_t g, uint32_t mask)
 {
@@ -107,6 +115,42 @@ __device__ __forceinline__ uint64_t spread_mask64(uint64_t g, uint64_t mask)
 
 // 2x2 on register bit B.  Register-slot controls `creg` are compile-time per
 // slot and uniform; `tok` is the per-lane control result.
+// Exact X on register bit B: exchange the two halves (no arithmetic).
+template <int B, int R, bool CTRL, typename V>
+__device__ __forceinline__ void xgate_reg_b(V (&a)[1 << R], uint32_t creg, bool tok)
+{
+    sfor<(1 << R)>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if constexpr (!(j & (1 << B))) {
+            constexpr int j1 = j | (1 << B);
+            if (!CTRL || ((uint32_t)j & creg) == creg) {
+                const V x0 = a[j], x1 = a[j1];
+                if (CTRL) {
+                    a[j] = csel(tok, x1, x0);
+                    a[j1] = csel(tok, x0, x1);
+                } else {
+                    a[j] = x1;
+                    a[j1] = x0;
+                }
+            }
+        }
+    });
+}
+
+template <int R, bool CTRL, typename V>
+__device__ __forceinline__ void xgate_reg(int b, V (&a)[1 << R], uint32_t creg, bool tok)
+{
+    switch (b) {
+    case 0: xgate_reg_b<0, R, CTRL>(a, creg, tok); break;
+    case 1: if constexpr (R > 1) xgate_reg_b<1, R, CTRL>(a, creg, tok); break;
+    case 2: if constexpr (R > 2) xgate_reg_b<2, R, CTRL>(a, creg, tok); break;
+    case 3: if constexpr (R > 3) xgate_reg_b<3, R, CTRL>(a, creg, tok); break;
+    case 4: if constexpr (R > 4) xgate_reg_b<4, R, CTRL>(a, creg, tok); break;
+    case 5: if constexpr (R > 5) xgate_reg_b<5, R, CTRL>(a, creg, tok); break;
+    default: break;
+    }
+}
+
 template <int B, int R, bool CTRL, typename V>
 __device__ __forceinline__ void oneq_reg_b(V (&a)[1 << R], V m00, V m01, V m10, V m11, uint32_t creg, bool tok)
 {
@@ -155,6 +199,22 @@ __device__ __forceinline__ double shfl_xor_f(double v, int addr)
     const int lo = __builtin_amdgcn_ds_bpermute(addr, (int)(b & 0xffffffffll));
     const int hi = __builtin_amdgcn_ds_bpermute(addr, (int)(b >> 32));
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Exact X on lane bit t: take the partner's amplitude.
+template <int R, bool CTRL, typename V>
+__device__ __forceinline__ void xgate_lane(int t, int lane, V (&a)[1 << R], uint32_t creg, bool tok)
+{
+    const int addr = (lane ^ (1 << t)) << 2;
+    sfor<(1 << R)>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if (!CTRL || ((uint32_t)j & creg) == creg) {
+            V p;
+            p.x = shfl_xor_f(a[j].x, addr);
+            p.y = shfl_xor_f(a[j].y, addr);
+            a[j] = CTRL ? csel(tok, p, a[j]) : p;
+        }
+    });
 }
 
 // 2x2 on lane bit t: each lane computes its own output from its amplitude
@@ -212,7 +272,7 @@ __device__ void dense_lds(typename CxT<T>::V* lds, int L, const DevOp& op, const
         if ((gb & op.c_tile) != op.c_tile) continue;
         V in[D];
 #pragma unroll
-        for (int s = 0; s < D; ++s) in[s] = lds[gb + toff[s]];
+        for (int s = 0; s < D; ++s) in[s] = lds[swz(gb + toff[s])];
 #pragma unroll
         for (int r = 0; r < D; ++r) {
             V acc;
@@ -224,7 +284,7 @@ __device__ void dense_lds(typename CxT<T>::V* lds, int L, const DevOp& op, const
                 acc.x += ur * in[s].x - ui * in[s].y;
                 acc.y += ur * in[s].y + ui * in[s].x;
             }
-            lds[gb + toff[r]] = acc;
+            lds[swz(gb + toff[r])] = acc;
         }
     }
 }
@@ -266,84 +326,124 @@ __device__ void diag_lds(typename CxT<T>::V* lds, int L, const DevOp& op, const 
 #pragma unroll
         for (int i = 0; i < 6; ++i)
             if (x & tmask[i]) idx |= 1u << i;
-        lds[x] = cmul(lds[x], ldc(tab, (int)idx));
+        lds[swz(x)] = cmul(lds[swz(x)], ldc(tab, (int)idx));
     }
 }
 
-// Dense 2^K x 2^K on tile positions with matrix cores.  The block is the
-// real embedding M (2^(K+1) square, rows/cols interleaved re,im) applied to
-// the tile viewed as a 2^(K+1) x 2^(L-K) real matrix (one column per group).
-// A fragments are pre-arranged by the host (rows permuted for f64 so that
-// both precisions return the same D layout): lane l, register i of the
-// result holds real row 4(l/16)+i of column l%16.  B operand: lane l holds
-// real row 4 ks + l/16 of column l%16.
+// Dense 2^K x 2^K on tile positions with matrix cores (four waves).  The block
+// is the real embedding M (2^(K+1) square, rows/cols interleaved re,im)
+// applied to the tile viewed as a 2^(K+1) x 2^(L-K) real matrix (one column
+// per group of 2^K amplitudes, 16 columns per column block).  The waves form
+// RW row groups x CW column groups.  A wave keeps the A fragments of all its
+// row blocks in registers for the whole operation and feeds every B value it
+// reads to all of them.  With RW = 1 every column block belongs to one wave,
+// which reads, multiplies and writes it back without synchronisation; with
+// RW > 1 the waves of a column group finish reading a chunk of column blocks
+// before any of them writes it (one barrier per chunk).
+// A fragments are pre-arranged by the host (rows permuted for f64 so both
+// precisions return the same D layout): lane l, register i of the result
+// holds real row 4(l/16)+i of column l%16; the B operand of lane l is real
+// row 4 ks + l/16 of column l%16.  LDS slots are swizzled (swz), whose
+// linearity turns every address into one XOR of a per-lane and a uniform part.
 template <int K, typename T>
 __device__ void mfma_lds(typename CxT<T>::V* lds, int L, const DevOp& op, const T* __restrict__ A, int lane,
-                         int wave, int nwaves)
+                         int wave)
 {
     using V = typename CxT<T>::V;
     using A4 = typename CxT<T>::A4;
-    constexpr int KS = 1 << (K - 1);   // k-steps of 4 real rows
-    constexpr int RB = 1 << (K - 3);   // row blocks of 16 real rows
-    uint32_t mask = 0;
+    constexpr int KS = 1 << (K - 1);           // k-steps of 4 real rows
+    constexpr int RB = 1 << (K - 3);           // row blocks of 16 real rows
+    constexpr int RW = sizeof(T) == 4 ? (K <= 5 ? 1 : 2) : (K <= 4 ? 1 : (K == 5 ? 2 : 4));
+    constexpr int CW = 4 / RW;                 // column groups
+    constexpr int RPW = RB / RW;               // row blocks per wave
+    constexpr int CH = RW == 1 ? 1 : 4;        // column blocks per barrier chunk
+    const int rg = wave % RW, cg = wave / RW;
+    const int ncb = 1 << (L - K - 4);
+    const int nper = (ncb + CW - 1) / CW;      // same for every wave
+    uint32_t mask = 0, bit[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) mask |= 1u << op.pos[j];
-    // offset of complex index s inside a group
-    auto toff = [&](uint32_t s) {
+    for (int j = 0; j < K; ++j) {
+        bit[j] = 1u << op.pos[j];
+        mask |= bit[j];
+    }
+    auto toff = [&](uint32_t s) {              // s is a compile-time constant at every call
         uint32_t o = 0;
 #pragma unroll
         for (int j = 0; j < K; ++j)
-            if (s & (1u << j)) o |= 1u << op.pos[j];
+            if (s & (1u << j)) o |= bit[j];
         return o;
     };
     const int krow = lane >> 4;
-    const uint32_t in_lane = (krow >> 1) ? (1u << op.pos[0]) : 0u;               // s bit 0
-    const uint32_t out_lane = ((krow & 1) ? (1u << op.pos[1]) : 0u) | ((krow >> 1) ? (1u << op.pos[2]) : 0u);
-    const uint32_t ncb = 1u << (L - K - 4);
-    for (uint32_t cb = wave; cb < ncb; cb += nwaves) {
-        const uint32_t col = cb * 16 + (lane & 15);
-        const uint32_t gb = spread_mask(col, mask);
-        const bool ok = (gb & op.c_tile) == op.c_tile;
-        T bv[KS];
+    const uint32_t in_sw = swz((krow >> 1) ? bit[0] : 0u);                           // bit 0 of s
+    const uint32_t out_sw = swz(((krow & 1) ? bit[1] : 0u) | ((krow >> 1) ? bit[2] : 0u));
+    const uint32_t part = (uint32_t)(krow & 1);                                       // re / im
+    T av[RPW][KS];
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            const V v = lds[gb + toff((uint32_t)(2 * ks)) + in_lane];
-            bv[ks] = (krow & 1) ? v.y : v.x;
-        }
-#pragma unroll 1
-        for (int rb = 0; rb < RB; ++rb) {
-            A4 acc = {0, 0, 0, 0};
+    for (int r = 0; r < RPW; ++r)
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                const T av = A[(rb * KS + ks) * 64 + lane];
-                if constexpr (sizeof(T) == 4)
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[ks], acc, 0, 0, 0);
-                else
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[ks], acc, 0, 0, 0);
+        for (int ks = 0; ks < KS; ++ks) av[r][ks] = A[((rg * RPW + r) * KS + ks) * 64 + lane];
+    const T* __restrict__ ldsf = reinterpret_cast<const T*>(lds);
+    for (int i0 = 0; i0 < nper; i0 += CH) {
+        A4 acc[RPW][CH];
+        uint32_t gsw[CH];
+        sfor<CH>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            const int blk = cg + (i0 + c) * CW;
+#pragma unroll
+            for (int r = 0; r < RPW; ++r) acc[r][c] = A4{0, 0, 0, 0};
+            gsw[c] = 0;
+            if (i0 + c < nper && blk < ncb) {
+                const uint32_t col = (uint32_t)blk * 16 + (lane & 15);
+                gsw[c] = swz(spread_mask(col, mask));
+                const uint32_t g_in = gsw[c] ^ in_sw;
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) {
+                    const T b = ldsf[2 * (g_in ^ swz(toff((uint32_t)(2 * ks)))) + part];
+#pragma unroll
+                    for (int r = 0; r < RPW; ++r) {
+                        if constexpr (sizeof(T) == 4)
+                            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[r][ks], b, acc[r][c], 0, 0, 0);
+                        else
+                            acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r][ks], b, acc[r][c], 0, 0, 0);
+                    }
+                }
             }
-            if (ok) {
-                const uint32_t o0 = gb + toff((uint32_t)(8 * rb)) + out_lane;
-                V w0, w1;
-                w0.x = acc[0];
-                w0.y = acc[1];
-                w1.x = acc[2];
-                w1.y = acc[3];
-                lds[o0] = w0;
-                lds[o0 + (1u << op.pos[0])] = w1;
+        });
+        if constexpr (RW > 1) __syncthreads();   // the chunk's B fragments are read
+        sfor<CH>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            const int blk = cg + (i0 + c) * CW;
+            if (i0 + c < nper && blk < ncb) {
+                const uint32_t col = (uint32_t)blk * 16 + (lane & 15);
+                if ((spread_mask(col, mask) & op.c_tile) == op.c_tile) {
+                    const uint32_t g_out = gsw[c] ^ out_sw;
+#pragma unroll
+                    for (int r = 0; r < RPW; ++r) {
+                        const int rb = rg * RPW + r;
+                        const uint32_t o0 = g_out ^ swz(toff((uint32_t)(8 * rb)));
+                        V w0, w1;
+                        w0.x = acc[r][c][0];
+                        w0.y = acc[r][c][1];
+                        w1.x = acc[r][c][2];
+                        w1.y = acc[r][c][3];
+                        lds[o0] = w0;
+                        lds[o0 ^ swz(bit[0])] = w1;
+                    }
+                }
             }
-        }
+        });
     }
 }
 
 template <typename T>
 __device__ void mfma_dispatch(typename CxT<T>::V* lds, int L, const DevOp& op, const T* __restrict__ A, int lane,
-                              int wave, int nwaves)
+                              int wave)
 {
     switch (op.a) {
-    case 3: mfma_lds<3, T>(lds, L, op, A, lane, wave, nwaves); break;
-    case 4: mfma_lds<4, T>(lds, L, op, A, lane, wave, nwaves); break;
-    case 5: mfma_lds<5, T>(lds, L, op, A, lane, wave, nwaves); break;
-    case 6: mfma_lds<6, T>(lds, L, op, A, lane, wave, nwaves); break;
+    case 3: mfma_lds<3, T>(lds, L, op, A, lane, wave); break;
+    case 4: mfma_lds<4, T>(lds, L, op, A, lane, wave); break;
+    case 5: mfma_lds<5, T>(lds, L, op, A, lane, wave); break;
+    case 6: mfma_lds<6, T>(lds, L, op, A, lane, wave); break;
     default: break;
     }
 }
@@ -448,7 +548,15 @@ tile_pass_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict_
                 const V m00 = ldc(c, 0), m01 = ldc(c, 1), m10 = ldc(c, 2), m11 = ldc(c, 3);
                 const bool ctrl = (op.c_lane | op.c_wave | op.c_reg) != 0;
                 const bool tok = ((uint32_t)lane & op.c_lane) == op.c_lane && ((uint32_t)wave & op.c_wave) == op.c_wave;
-                if (op.type == OP_1Q_REG) {
+                if (op.b == 1) {   // exact X: exchange only
+                    if (op.type == OP_1Q_REG) {
+                        if (ctrl) xgate_reg<R, true>(op.a, a, op.c_reg, tok);
+                        else xgate_reg<R, false>(op.a, a, 0u, true);
+                    } else {
+                        if (ctrl) xgate_lane<R, true>(op.a, lane, a, op.c_reg, tok);
+                        else xgate_lane<R, false>(op.a, lane, a, 0u, true);
+                    }
+                } else if (op.type == OP_1Q_REG) {
                     if (ctrl)
                         oneq_reg<R, true>(op.a, a, m00, m01, m10, m11, op.c_reg, tok);
                     else
@@ -458,6 +566,35 @@ tile_pass_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict_
                         oneq_lane<R, true>(op.a, lane, a, m00, m01, m10, m11, op.c_reg, tok);
                     else
                         oneq_lane<R, false>(op.a, lane, a, m00, m01, m10, m11, 0u, true);
+                }
+                break;
+            }
+            case OP_CPHASE: {
+                // phase on the amplitudes whose masked bits are all 1; the
+                // register part of the condition is uniform per slot
+                const bool tok = ((uint32_t)lane & op.c_lane) == op.c_lane && ((uint32_t)wave & op.c_wave) == op.c_wave;
+                const bool thr = (op.c_lane | op.c_wave) != 0;
+                const uint32_t creg = op.c_reg;
+                // the multiplier is 1 where the lane's bits do not match
+                V ph = ldc(coef + op.coef, 0);
+                if (thr) {
+                    ph.x = tok ? ph.x : (T)1;
+                    ph.y = tok ? ph.y : (T)0;
+                }
+                if (op.b == 1) {   // -1: flip signs (lanes that do not match multiply by +1)
+                    const T sgn = ph.x;
+                    sfor<NR>([&](auto jc) {
+                        constexpr int j = decltype(jc)::value;
+                        if (((uint32_t)j & creg) == creg) {
+                            a[j].x *= sgn;
+                            a[j].y *= sgn;
+                        }
+                    });
+                } else {
+                    sfor<NR>([&](auto jc) {
+                        constexpr int j = decltype(jc)::value;
+                        if (((uint32_t)j & creg) == creg) a[j] = cmul(a[j], ph);
+                    });
                 }
                 break;
             }
@@ -477,14 +614,43 @@ tile_pass_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict_
                         else rm[q] = 1u << v;
                     }
                 }
-                sfor<NR>([&](auto jc) {
-                    constexpr int j = decltype(jc)::value;
-                    uint32_t idx = ithr;
+                // table bits held in registers: at most two take the fast path
+                // (the four candidate phases are loaded once per thread and
+                // selected per slot with uniform conditions)
+                int nq = 0, qa = -1, qb = -1;
 #pragma unroll
-                    for (int q = 0; q < 6; ++q)
-                        if ((uint32_t)j & rm[q]) idx |= 1u << q;
-                    a[j] = cmul(a[j], ldc(tab, (int)idx));
-                });
+                for (int q = 0; q < 6; ++q)
+                    if (rm[q]) {
+                        if (nq == 0) qa = q;
+                        else if (nq == 1) qb = q;
+                        ++nq;
+                    }
+                if (nq <= 2) {
+                    const uint32_t ba = qa >= 0 ? 1u << qa : 0u, bb = qb >= 0 ? 1u << qb : 0u;
+                    const uint32_t ma = qa >= 0 ? rm[qa] : 0u, mb = qb >= 0 ? rm[qb] : 0u;
+                    V pv[4];
+                    pv[0] = ldc(tab, (int)ithr);
+                    pv[1] = ldc(tab, (int)(ithr | ba));
+                    pv[2] = ldc(tab, (int)(ithr | bb));
+                    pv[3] = ldc(tab, (int)(ithr | ba | bb));
+                    sfor<NR>([&](auto jc) {
+                        constexpr int j = decltype(jc)::value;
+                        const int r = (((uint32_t)j & ma) ? 1 : 0) | (((uint32_t)j & mb) ? 2 : 0);   // uniform
+                        if (r == 0) a[j] = cmul(a[j], pv[0]);
+                        else if (r == 1) a[j] = cmul(a[j], pv[1]);
+                        else if (r == 2) a[j] = cmul(a[j], pv[2]);
+                        else a[j] = cmul(a[j], pv[3]);
+                    });
+                } else {
+                    sfor<NR>([&](auto jc) {
+                        constexpr int j = decltype(jc)::value;
+                        uint32_t idx = ithr;
+#pragma unroll
+                        for (int q = 0; q < 6; ++q)
+                            if ((uint32_t)j & rm[q]) idx |= 1u << q;
+                        a[j] = cmul(a[j], ldc(tab, (int)idx));
+                    });
+                }
                 break;
             }
             case OP_REMAP:
@@ -508,7 +674,11 @@ tile_pass_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict_
             }
         }
         {
-            V* dst = st + base + ms.tphys;
+            // an opaque copy of the thread offset keeps the compiler from
+            // holding every load address live across the operation loop
+            uint64_t tp = ms.tphys;
+            asm volatile("" : "+v"(tp));
+            V* dst = st + base + tp;
             sfor<NR>([&](auto jc) { dst[reg_phys(ms, decltype(jc)::value)] = a[decltype(jc)::value]; });
         }
     }
@@ -565,12 +735,40 @@ hipError_t launch_tile_pass(int prec, int R, int W, void* state, const PassHdr* 
 // on it there.  Used for passes that hold dense multi-qubit blocks.
 // ---------------------------------------------------------------------------
 
+// Physical offset of upper tile bits v (bit j of v -> physical bit up[j]).
+__device__ __forceinline__ uint64_t dep_up(uint32_t v, const int32_t* __restrict__ up, int nup)
+{
+    uint64_t o = 0;
+    for (int j = 0; j < nup; ++j)
+        if ((v >> j) & 1u) o |= 1ull << up[j];
+    return o;
+}
+
+__device__ __forceinline__ uint64_t tile_base(uint64_t tile, const PassHdr* __restrict__ hp)
+{
+    uint64_t base = 0;
+    for (int r = 0; r < hp->nruns; ++r) {
+        const uint64_t field = (tile >> hp->run_gshift[r]) & ((1ull << hp->run_len[r]) - 1ull);
+        base |= field << hp->run_start[r];
+    }
+    return base;
+}
+
+// Amplitudes per thread of the largest LDS tile (2^13 c64, 2^12 c128).
+template <typename T> constexpr int kLdsEpt = sizeof(T) == 4 ? 32 : 16;
+
+// LDS tile pass, persistent and software-pipelined: a work-group stages the
+// pass's matrix-core fragments and diagonal tables in LDS once, then loops
+// over tiles; while the operations of tile t run on its LDS copy, the loads
+// of the next tile are already in flight into registers.  Tile element
+// e = 256 u + tid has physical bits 0..5 = e & 63 and bit 6+j = up_phys[j].
 template <typename T>
 __global__ void __launch_bounds__(256)
 tile_lds_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict__ hp, const DevOp* __restrict__ ops,
                 const T* __restrict__ coef, uint64_t ntiles)
 {
     using V = typename CxT<T>::V;
+    constexpr int EPT = kLdsEpt<T>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V* lds = reinterpret_cast<V*>(smem_raw);
     const int tid = threadIdx.x;
@@ -580,47 +778,97 @@ tile_lds_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict__
     const int nops = hp->nops;
     const DevOp* __restrict__ prog = ops + hp->op0;
     const uint32_t N = 1u << L;
-    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        uint64_t base = 0;
-        for (int r = 0; r < hp->nruns; ++r) {
-            const uint64_t field = (tile >> hp->run_gshift[r]) & ((1ull << hp->run_len[r]) - 1ull);
-            base |= field << hp->run_start[r];
-        }
-        // tile element e: low 6 bits = physical bits 0..5, bit 6+u = up_phys[u]
-        for (uint32_t e = tid; e < N; e += 256) {
-            uint64_t p = base + (e & 63u);
-            for (int u = 0; u < nup; ++u)
-                if ((e >> (6 + u)) & 1u) p |= 1ull << hp->up_phys[u];
-            lds[e] = st[p];
-        }
+    T* lcoef = reinterpret_cast<T*>(smem_raw + ((size_t)N * sizeof(V)));
+    {
+        const T* __restrict__ src = coef + hp->coef_src;
+        for (int i = tid; i < hp->coef_n; i += 256) lcoef[i] = src[i];
+    }
+    const uint64_t dep_thr = dep_up((uint32_t)(tid >> 6), hp->up_phys, nup);
+    // element 256 u + tid: bit b of u selects physical bit up_phys[2 + b]
+    uint64_t ub[5];
+#pragma unroll
+    for (int b = 0; b < 5; ++b) ub[b] = (2 + b < nup) ? (1ull << hp->up_phys[2 + b]) : 0ull;
+    auto uoff = [&](int u) {
+        uint64_t o = 0;
+#pragma unroll
+        for (int b = 0; b < 5; ++b)
+            if (u & (1 << b)) o += ub[b];
+        return o;
+    };
+    const uint32_t tsw = swz((uint32_t)tid);
+    T pr[EPT], pi[EPT];
+    auto fetch = [&](uint64_t tile) {
+        const V* __restrict__ src = st + tile_base(tile, hp) + lane + dep_thr;
+        sfor<EPT>([&](auto uc) {
+            constexpr int u = decltype(uc)::value;
+            if (256u * u < N) {
+                const V x = src[uoff(u)];
+                pr[u] = x.x;
+                pi[u] = x.y;
+            }
+        });
+    };
+    uint64_t tile = blockIdx.x;
+    if (tile < ntiles) fetch(tile);
+    for (; tile < ntiles; tile += gridDim.x) {
+        const uint64_t base = tile_base(tile, hp);
+        sfor<EPT>([&](auto uc) {
+            constexpr int u = decltype(uc)::value;
+            if (256u * u < N) {
+                V x;
+                x.x = pr[u];
+                x.y = pi[u];
+                lds[swz(256u * u) ^ tsw] = x;
+            }
+        });
         __syncthreads();
+        if (tile + gridDim.x < ntiles) fetch(tile + gridDim.x);
         for (int i = 0; i < nops; ++i) {
             const DevOp op = prog[i];
             if ((base & op.c_glob) != op.c_glob) continue;
+            const T* cf = op.b ? lcoef + op.coef : coef + op.coef;
             if (op.type == OP_DENSE_LDS)
                 dense_lds_dispatch<T>(lds, L, op, coef + op.coef, tid, 256);
             else if (op.type == OP_MFMA)
-                mfma_dispatch<T>(lds, L, op, coef + op.coef, lane, wave, 4);
+                mfma_dispatch<T>(lds, L, op, cf, lane, wave);
             else if (op.type == OP_DIAG_LDS)
-                diag_lds<T>(lds, L, op, coef + op.coef, base, tid, 256);
+                diag_lds<T>(lds, L, op, cf, base, tid, 256);
             __syncthreads();
         }
-        for (uint32_t e = tid; e < N; e += 256) {
-            uint64_t p = base + (e & 63u);
-            for (int u = 0; u < nup; ++u)
-                if ((e >> (6 + u)) & 1u) p |= 1ull << hp->up_phys[u];
-            st[p] = lds[e];
+        {
+            V* __restrict__ dst = st + base + lane + dep_thr;
+            sfor<EPT>([&](auto uc) {
+                constexpr int u = decltype(uc)::value;
+                if (256u * u < N) dst[uoff(u)] = lds[swz(256u * u) ^ tsw];
+            });
         }
         __syncthreads();
     }
 }
 
-hipError_t launch_tile_lds(int prec, void* state, const PassHdr* hdr, const DevOp* ops, const void* coef,
-                           uint64_t ntiles, int L, int grid_cap, hipStream_t s)
+static int g_num_cus = 0;
+
+static int num_cus()
 {
-    const size_t bytes = (size_t(1) << L) * (prec == 0 ? 8 : 16);
-    uint64_t grid = ntiles;
+    if (g_num_cus == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            g_num_cus = v;
+        else
+            g_num_cus = 256;
+    }
+    return g_num_cus;
+}
+
+hipError_t launch_tile_lds(int prec, void* state, const PassHdr* hdr, const DevOp* ops, const void* coef,
+                           uint64_t ntiles, int L, int lds_bytes, int grid_cap, hipStream_t s)
+{
+    (void)L;
+    // persistent grid: as many work-groups as fit on the chip at this LDS size
+    const int per_cu = std::max(1, std::min(8, tile_max_lds_bytes() / std::max(lds_bytes, 1)));
+    uint64_t grid = std::min<uint64_t>(ntiles, (uint64_t)num_cus() * per_cu);
     if (grid_cap > 0 && grid > (uint64_t)grid_cap) grid = (uint64_t)grid_cap;
+    if (grid == 0) grid = 1;
     if (prec == 0) {
         static bool done = false;
         if (!done) {
@@ -628,7 +876,7 @@ hipError_t launch_tile_lds(int prec, void* state, const PassHdr* hdr, const DevO
                                       tile_max_lds_bytes());
             done = true;
         }
-        hipLaunchKernelGGL(tile_lds_kernel<float>, dim3((unsigned)grid), dim3(256), bytes, s,
+        hipLaunchKernelGGL(tile_lds_kernel<float>, dim3((unsigned)grid), dim3(256), lds_bytes, s,
                            reinterpret_cast<float2*>(state), hdr, ops, reinterpret_cast<const float*>(coef), ntiles);
     } else {
         static bool done = false;
@@ -637,7 +885,7 @@ hipError_t launch_tile_lds(int prec, void* state, const PassHdr* hdr, const DevO
                                       tile_max_lds_bytes());
             done = true;
         }
-        hipLaunchKernelGGL(tile_lds_kernel<double>, dim3((unsigned)grid), dim3(256), bytes, s,
+        hipLaunchKernelGGL(tile_lds_kernel<double>, dim3((unsigned)grid), dim3(256), lds_bytes, s,
                            reinterpret_cast<double2*>(state), hdr, ops, reinterpret_cast<const double*>(coef), ntiles);
     }
     return hipGetLastError();
@@ -657,7 +905,7 @@ __device__ void run_ops_lds(typename CxT<T>::V* lds, int n, const DevOp* __restr
         if (op.type == OP_DENSE_LDS)
             dense_lds_dispatch<T>(lds, n, op, coef + op.coef, tid, nthr);
         else if (op.type == OP_MFMA)
-            mfma_dispatch<T>(lds, n, op, coef + op.coef, lane, wave, nthr / 64);
+            mfma_dispatch<T>(lds, n, op, coef + op.coef, lane, wave);
         else if (op.type == OP_DIAG_LDS)
             diag_lds<T>(lds, n, op, coef + op.coef, 0ull, tid, nthr);
         __syncthreads();
@@ -673,10 +921,10 @@ state_lds_kernel(typename CxT<T>::V* __restrict__ st, int n, const DevOp* __rest
     extern __shared__ __align__(16) unsigned char smem_raw[];
     V* lds = reinterpret_cast<V*>(smem_raw);
     const uint32_t N = 1u << n;
-    for (uint32_t x = threadIdx.x; x < N; x += blockDim.x) lds[x] = st[x];
+    for (uint32_t x = threadIdx.x; x < N; x += blockDim.x) lds[swz(x)] = st[x];
     __syncthreads();
     run_ops_lds<T>(lds, n, ops, nops, coef, threadIdx.x, blockDim.x);
-    for (uint32_t x = threadIdx.x; x < N; x += blockDim.x) st[x] = lds[x];
+    for (uint32_t x = threadIdx.x; x < N; x += blockDim.x) st[x] = lds[swz(x)];
 }
 
 hipError_t launch_state_lds(int prec, void* state, int n, const DevOp* ops, int nops, const void* coef,

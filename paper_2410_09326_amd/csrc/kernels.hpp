@@ -21,7 +21,7 @@ hipError_t launch_tile_pass(int prec, int R, int W, void* state, const PassHdr* 
 
 // LDS tile pass (dense blocks): tile of 2^L amplitudes in LDS, 256 threads.
 hipError_t launch_tile_lds(int prec, void* state, const PassHdr* hdr, const DevOp* ops, const void* coef,
-                           uint64_t ntiles, int L, int grid_cap, hipStream_t s);
+                           uint64_t ntiles, int L, int lds_bytes, int grid_cap, hipStream_t s);
 
 // Whole state in one work-group's LDS (n <= 13 for c64, <= 12 for c128).
 hipError_t launch_state_lds(int prec, void* state, int n, const DevOp* ops, int nops, const void* coef,

@@ -202,6 +202,8 @@ static Err lower(int n, const qops_gate* g, size_t ng, int swap_mode, std::vecto
                 const size_t cpart = idx >> k;
                 if (cpart == (((size_t)1 << x.n_ctrl) - 1)) o.m[idx] = u[(idx & (d - 1)) * (d + 1)];
             }
+            o.cphase = true;
+            for (size_t idx = 0; idx + 1 < o.m.size(); ++idx) o.cphase = o.cphase && o.m[idx] == cd(1, 0);
         } else if (x.kind == QOPS_CX) {
             o.kind = LOp::ONEQ;
             o.k = 1;
@@ -272,6 +274,8 @@ static bool merge_diag(LOp& y, const LOp& x)
     for (int j = 0; j < nb; ++j) y.t[j] = bits[j];
     y.m.swap(tab);
     y.nmerged += x.nmerged;
+    y.cphase = true;
+    for (size_t idx = 0; idx + 1 < y.m.size(); ++idx) y.cphase = y.cphase && y.m[idx] == cd(1, 0);
     return true;
 }
 
@@ -302,6 +306,7 @@ static void merge_ops(std::vector<LOp>& in, std::vector<LOp>& out)
                     y.kind = LOp::ONEQ;
                     y.k = 1;
                     y.cmask = 0;
+                    y.cphase = false;
                     y.m.swap(p);
                     y.nmerged += x.nmerged;
                     y.gkind = x.gkind;
@@ -320,7 +325,13 @@ static void merge_ops(std::vector<LOp>& in, std::vector<LOp>& out)
             for (int j = (int)out.size() - 1, c = 0; j >= 0 && c < kScan; --j, ++c) {
                 LOp& y = out[j];
                 if (y.dead) continue;
-                if (y.kind == LOp::DIAG && diag_cand < 0) {
+                // controlled phases merge only with a controlled phase on the
+                // same bits (the product is again one); general tables merge
+                // with general tables
+                bool same_bits = y.kind == LOp::DIAG && y.k == x.k;
+                for (int b = 0; same_bits && b < x.k; ++b) same_bits = y.t[b] == x.t[b];
+                const bool compatible = (!x.cphase && !y.cphase) || (x.cphase && y.cphase && same_bits);
+                if (y.kind == LOp::DIAG && diag_cand < 0 && compatible) {
                     LOp probe = y;
                     if (merge_diag(probe, x)) {
                         diag_cand = j;
@@ -416,12 +427,14 @@ static void fill_runs(int n, const std::vector<int>& up, PassHdr& h)
 // Vector-ALU dense blocks are compiled for k <= 4 (c64) / k <= 3 (c128);
 // matrix-core blocks need k >= 3 and at least 16 groups (L >= k + 4).
 static bool valu_ok(const Plan& p, int k) { return p.prec == 0 ? k <= 4 : k <= 3; }
+// the matrix-core stage is compiled for tiles of up to 2^13 (c64) / 2^12
+// (c128) amplitudes
 static bool mfma_possible(int k, int L) { return k >= 3 && L >= k + 4; }
 static bool use_mfma_for(const Plan& p, int k, int L)
 {
     if (!mfma_possible(k, L)) return false;
     if (!valu_ok(p, k)) return true;
-    return p.par.use_mfma && k >= 4;
+    return p.par.use_mfma != 0;
 }
 static bool lds_capable(const Plan& p, const LOp& o, int L)
 {
@@ -581,7 +594,20 @@ static void emit_tile_reg(Plan& p, PassPlan& pp)
             }
             enc_ctrl(o.cmask);
             d.coef = push_coef(p, o.m);
-            pp.flops += 16.0 * std::ldexp(1.0, p.n);
+            const bool is_x = o.m[0] == cd(0) && o.m[1] == cd(1) && o.m[2] == cd(1) && o.m[3] == cd(0);
+            d.b = is_x ? 1 : 0;
+            if (!is_x) pp.flops += 16.0 * std::ldexp(1.0, p.n - __builtin_popcountll(o.cmask));
+        } else if (o.cphase) {
+            // phase on the all-ones pattern of the table bits: a control mask
+            d.type = OP_CPHASE;
+            uint64_t bm = 0;
+            for (int j = 0; j < o.k; ++j) bm |= 1ull << o.t[j];
+            enc_ctrl(bm);
+            const cd ph = o.m.back();
+            d.coef = push_coef(p, {ph});
+            d.b = ph == cd(-1, 0) ? 1 : 0;
+            pp.n_diag_ops++;
+            pp.flops += 6.0 * std::ldexp(1.0, p.n - o.k);
         } else {   // DIAG
             d.type = OP_DIAG;
             d.a = o.k;
@@ -610,6 +636,19 @@ static void emit_tile_reg(Plan& p, PassPlan& pp)
     p.hdrs.push_back(h);
 }
 
+// Bytes of coefficients an LDS tile pass stages in LDS for an op (matrix-core
+// fragments and diagonal tables); 0 for ops that read theirs with scalar loads.
+static size_t staged_bytes(const Plan& p, const LOp& o, int L)
+{
+    const size_t sz = p.prec == 0 ? 4 : 8;
+    if (o.kind == LOp::DIAG) return (size_t(2) << o.k) * sz;
+    const int k = o.kind == LOp::PSWAP ? 2 : o.k;
+    if (o.kind == LOp::DENSE && use_mfma_for(p, k, L)) return (size_t(1) << (2 * (k + 1))) * sz;
+    return 0;
+}
+
+static size_t lds_budget() { return 160 * 1024; }
+
 static void emit_tile_lds(Plan& p, PassPlan& pp)
 {
     PassHdr h;
@@ -628,7 +667,30 @@ static void emit_tile_lds(Plan& p, PassPlan& pp)
     };
     for (int li : pp.lop) emit_lds_op(p, p.lops[li], pp.L, tpos, pp);
     h.nops = (int)p.dops.size() - h.op0;
-    h.lds_bytes = (1 << pp.L) * (p.prec == 0 ? 8 : 16);
+    // stage the per-lane coefficients (matrix-core fragments, diagonal
+    // tables) contiguously, as far as they fit next to the tile in LDS
+    const size_t sz = p.prec == 0 ? 4 : 8;
+    const size_t tile_bytes = (size_t(1) << pp.L) * 2 * sz;
+    size_t room = lds_budget() > tile_bytes ? (lds_budget() - tile_bytes) / sz : 0;
+    h.coef_src = (int)p.coef.size();
+    int staged = 0;
+    for (int i = h.op0; i < h.op0 + h.nops; ++i) {
+        DevOp& d = p.dops[i];
+        d.b = 0;
+        if (d.type != OP_MFMA && d.type != OP_DIAG_LDS) continue;
+        size_t cnt;
+        if (d.type == OP_MFMA) cnt = size_t(1) << (2 * (d.a + 1));
+        else cnt = size_t(2) << d.a;
+        if (cnt > room) continue;
+        const int off = (int)p.coef.size();
+        p.coef.insert(p.coef.end(), p.coef.begin() + d.coef, p.coef.begin() + d.coef + cnt);
+        d.coef = off - h.coef_src;
+        d.b = 1;
+        room -= cnt;
+        staged += (int)cnt;
+    }
+    h.coef_n = staged;
+    h.lds_bytes = (int)(tile_bytes + (size_t)staged * sz);
     pp.op0 = h.op0;
     pp.nops = h.nops;
     pp.hdr = (int)p.hdrs.size();
@@ -673,6 +735,9 @@ static void emit_sweep(Plan& p, PassPlan& pp)
 // ---------------------------------------------------------------------------
 // Packing
 // ---------------------------------------------------------------------------
+
+static size_t staged_bytes(const Plan& p, const LOp& o, int L);
+static size_t lds_budget();
 
 static void pick_reg_variant(int n, int prec, int want_up, int& R, int& W)
 {
@@ -779,6 +844,7 @@ static void pack(Plan& p)
     cur.W = W;
     uint64_t S = 0;
     bool dense = false;
+    size_t staged = 0;
     auto flush = [&]() {
         if (!cur.lop.empty()) {
             finish_pass(p, cur, S, dense);
@@ -789,6 +855,7 @@ static void pack(Plan& p)
         cur.W = W;
         S = 0;
         dense = false;
+        staged = 0;
     };
     for (size_t i = 0; i < p.lops.size(); ++i) {
         const LOp& o = p.lops[i];
@@ -809,15 +876,21 @@ static void pack(Plan& p)
                 if (o.t[j] >= 6) need |= 1ull << o.t[j];
         const bool d2 = dense || o.kind == LOp::DENSE;
         const int cap = d2 ? cap_lds : cap_reg;
-        if (__builtin_popcountll(S | need) > cap) {
+        // an LDS pass also keeps its matrix-core fragments next to the tile
+        const size_t sb = staged_bytes(p, o, 6 + cap_lds);
+        const size_t tile_bytes = (size_t(1) << (6 + cap_lds)) * (p.prec == 0 ? 8 : 16);
+        const bool lds_full = d2 && staged + sb + tile_bytes > lds_budget() && sb > 0 && staged > 0;
+        if (__builtin_popcountll(S | need) > cap || lds_full) {
             flush();
             cur.lop.push_back((int)i);
             S = need;
             dense = o.kind == LOp::DENSE;
+            staged = sb;
         } else {
             cur.lop.push_back((int)i);
             S |= need;
             dense = d2;
+            staged += sb;
         }
     }
     flush();

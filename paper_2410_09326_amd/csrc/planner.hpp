@@ -22,6 +22,7 @@ struct LOp {
     int gate = -1;             // first source gate
     int gkind = -1;            // kind of the first source gate
     int nmerged = 1;           // source gates folded into this op
+    bool cphase = false;       // DIAG: table is 1 except its last entry (all bits 1)
     bool dead = false;
     uint64_t touch() const;    // every physical bit the op reads or conditions on
     uint64_t tmask() const;    // non-diagonal target bits (ONEQ/DENSE/PSWAP)

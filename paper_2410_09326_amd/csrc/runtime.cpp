@@ -89,7 +89,8 @@ int32_t launch_pass(qops_sim* h, const Plan& p, const PassPlan& pp)
     }
     case PASS_TILE_LDS: {
         const uint64_t ntiles = 1ull << (p.n - pp.L);
-        e = launch_tile_lds(p.prec, h->state, dh + pp.hdr, dops, p.d_coef, ntiles, pp.L, h->grid_cap, h->stream);
+        e = launch_tile_lds(p.prec, h->state, dh + pp.hdr, dops, p.d_coef, ntiles, pp.L, p.hdrs[pp.hdr].lds_bytes,
+                            h->grid_cap, h->stream);
         break;
     }
     case PASS_STATE_LDS:
@@ -159,7 +160,7 @@ PlanParams params_from(const qops_plan_opts* o, int n, int prec)
             par.R = std::max(4, o->tile_upper);
             par.W = 0;
         }
-        par.L_lds = std::min(6 + o->tile_upper, prec == QOPS_C64 ? 14 : 13);
+        par.L_lds = std::min(6 + o->tile_upper, prec == QOPS_C64 ? 13 : 12);
     }
     par.max_fuse_k = o->max_fuse_k > 0 ? o->max_fuse_k : 1;
     par.use_mfma = o->use_mfma;

@@ -41,7 +41,7 @@ def check_state(got, ref, prec, what=""):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("n", [4, 6, 9, 12])
+@pytest.mark.parametrize("n", [4, 6, 7, 8, 9, 10, 12])
 def test_small_state_in_lds(q, n, prec):
     c = W.random_mixed(100 + n, n, 120, max_dense_k=min(6, n))
     got, _ = run_gpu(q, c, prec)

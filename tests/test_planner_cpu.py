@@ -116,10 +116,14 @@ def test_single_qubit_merging_and_diag_fusion_counts():
     gates += [("cz", (0, 1)), ("cz", (2, 3)), ("cp", (4, 5), (0.2,))]
     plan = q.Plan(n, gates)
     ops = plan.ops()
-    # all one-qubit gates on qubit 3 collapse to one 2x2; S on 9 to one diagonal;
-    # the three two-qubit diagonals fuse into one table
-    assert len(ops) <= 3
+    # all one-qubit gates on qubit 3 collapse to one 2x2; the five S on 9 to one
+    # controlled phase; controlled phases on different bits stay separate
+    # (cheaper per amplitude than a fused table)
+    assert len(ops) == 5
     assert sum(o["n_merged"] for o in ops) == len(gates)
+    gates2 = [("rzz", (0, 1), (0.3,)), ("rz", (2,), (0.2,)), ("rzz", (1, 2), (0.1,))]
+    ops2 = q.Plan(n, gates2).ops()
+    assert len(ops2) == 1 and ops2[0]["k"] == 3          # general tables fuse
 
 
 def test_pass_packing_respects_tile_width():
