@@ -92,6 +92,63 @@ def cpu_baseline(circ, seconds: float):
                       f"as the complex64 path's 2*2^n*8 per block)", "seconds": el, "blocks": done}
 
 
+MODELS = os.path.join(ROOT, "paper_2410_09326_amd", "models")
+
+
+def learned_vs_plain(n_circ: int):
+    """Plans seeded 32-qubit complex64 depth-60 circuits (U3/CZ/SWAP/RZZ
+    layers) twice -- priced by the plain cost table fitted to the shipped
+    profiling corpus, and by the trained perceptron -- and times both plans on
+    the GPU (best of two runs each).  Both runs are checked to agree."""
+    import numpy as np
+    import torch
+    import paper_2410_09326_amd as q
+    from workloads import circuits as W
+    model = q.CostModel.load(os.path.join(MODELS, "cost_mlp.bin"))
+    prof = q.Profile.load(os.path.join(MODELS, "corpus_profile.bin"))
+    with open(os.path.join(MODELS, "cost_model_summary.json")) as fh:
+        summ = json.load(fh)
+    n = 32
+    sim = q.Simulator(n, q.C64)
+    t_plain = t_learned = t_fused = 0.0
+    detail = []
+    for i in range(n_circ):
+        c = W.eval_circuit(9000 + i, n=n, depth=60)
+        plans = {"plain": q.Plan(n, c.gates, precision=q.C64, mode=q.PLAN_PROFILED, profile=prof),
+                 "learned": q.Plan(n, c.gates, precision=q.C64, mode=q.PLAN_LEARNED, model=model),
+                 "fused": q.Plan(n, c.gates, precision=q.C64)}
+        times, zs = {}, {}
+        for name, plan in plans.items():
+            best = None
+            for _ in range(2):
+                sim.init_basis(0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                sim.run(plan)
+                sim.synchronize()
+                el = time.perf_counter() - t0
+                best = el if best is None else min(best, el)
+            zs[name] = sim.expect_z()
+            times[name] = best
+        agree = float(max(np.max(np.abs(zs["plain"] - zs["learned"])), np.max(np.abs(zs["plain"] - zs["fused"]))))
+        t_plain += times["plain"]
+        t_learned += times["learned"]
+        t_fused += times["fused"]
+        detail.append({"seed": 9000 + i, "plain_ms": round(times["plain"] * 1e3, 2),
+                       "learned_ms": round(times["learned"] * 1e3, 2), "fused_ms": round(times["fused"] * 1e3, 2),
+                       "plain_passes": plans["plain"].stats()["n_passes"],
+                       "learned_passes": plans["learned"].stats()["n_passes"],
+                       "plain_predicted_ms": round(plans["plain"].stats()["predicted_s"] * 1e3, 2),
+                       "learned_predicted_ms": round(plans["learned"].stats()["predicted_s"] * 1e3, 2),
+                       "max_abs_expz_diff": agree})
+    sim.close()
+    return {"workload": "32-qubit complex64 random U3/CZ/SWAP/RZZ layers, depth 60 (seeds 9000+)",
+            "speedup": round(t_plain / t_learned, 4), "plain_ms": round(t_plain * 1e3, 2),
+            "learned_ms": round(t_learned * 1e3, 2), "fused_heuristic_ms": round(t_fused * 1e3, 2),
+            "heldout_mape_learned": round(summ["mape_learned"], 4), "heldout_mape_plain": round(summ["mape_plain"], 4),
+            "corpus_passes": summ["passes"], "circuits": detail}
+
+
 def main() -> None:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +157,8 @@ def main() -> None:
     ap.add_argument("--workload", default="haar30")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-learned-eval", action="store_true")
+    ap.add_argument("--eval-circuits", type=int, default=2)
     ap.add_argument("--dump-passes", default="", help="write the last step's pass records (JSON) here")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 2^30 x 8-byte device copy (counter calibration)")
@@ -209,6 +268,10 @@ def main() -> None:
                         "launches_per_step": v["launches"] // args.steps} for k, v in per.items()},
         "roofline": roof,
     }
+    if not args.no_learned_eval:
+        sim.close()
+        torch.cuda.empty_cache()
+        out["learned_vs_plain"] = learned_vs_plain(args.eval_circuits)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(circ, args.cpu_seconds)
         out["cpu_baseline"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in cb.items()

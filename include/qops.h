@@ -148,6 +148,11 @@ typedef struct qops_plan_opts {
     int32_t use_mfma;      /* 1 = matrix cores for dense blocks with k >= 4
                               (default), 0 = vector ALU only                  */
     int32_t check_unitary; /* 1 = reject non-unitary DENSE input (1e-9)       */
+    int32_t remap;         /* 1 = before the gates, move the six qubits that
+                              non-diagonal gates target most often into
+                              physical bits 0..5 (held by every tile pass),
+                              by physical bit exchanges; PROFILED / LEARNED
+                              modes decide this themselves                    */
     const qops_profile* profile;  /* PROFILED / LEARNED pricing input         */
     const qops_model* model;      /* LEARNED pricing input                    */
 } qops_plan_opts;
@@ -262,6 +267,47 @@ int32_t qops_profile_dump(const qops_profile* pr, const char* path);
  * profiling runs). */
 int32_t qops_profile_merge(qops_profile* dst, const qops_profile* src);
 int32_t qops_profile_free(qops_profile* pr);
+
+/* ------------------------------------------------------ cost model ---- */
+/* A 3-layer perceptron, 64 -> 128 -> 128 -> 1 with ReLU, predicting the
+ * natural log of a pass's run time (seconds) from the 64 pass features of
+ * qops_profile_features.  Parameters (float) in this order: W1 [128 x 64]
+ * row-major, b1 [128], W2 [128 x 128], b2 [128], W3 [1 x 128], b3 [1];
+ * inputs are standardised with per-feature mean/sd before the first layer.
+ * Training runs on the GPU (forward, backward of the mean squared error,
+ * Adam) with fixed summation orders.  Prices candidate plans in LEARNED mode
+ * (the choice of which optimisation to switch on, paper Sec. III-D). */
+int32_t qops_mlp_num_params(size_t* n);
+/* params may be null (all zero) or hold qops_mlp_num_params floats. */
+int32_t qops_mlp_create(const float* params, size_t n, qops_model** out);
+int32_t qops_mlp_set_normalization(qops_model* m, const float* mu, const float* sd);
+/* Any of the outputs may be null. */
+int32_t qops_mlp_get_params(const qops_model* m, float* params, float* mu, float* sd);
+/* Loss (1/rows) sum (y - t)^2 and its gradient w.r.t. every parameter, on
+ * the GPU (host arrays in and out).  Blocking. */
+int32_t qops_mlp_grad(qops_model* m, const float* X, const float* t, int32_t rows, float* grads, float* loss);
+/* Trains with Adam (beta 0.9/0.999, eps 1e-8) for `epochs` passes over the
+ * rows in batches of `batch`, reshuffled each epoch from `seed`.  Blocking. */
+int32_t qops_mlp_train(qops_model* m, const float* X, const float* t, int32_t rows, int32_t epochs, int32_t batch,
+                       float lr, uint64_t seed, float* final_loss);
+/* out[r] = predicted log seconds of row r (on the GPU).  Blocking. */
+int32_t qops_mlp_predict(qops_model* m, const float* X, int32_t rows, float* out);
+int32_t qops_model_save(const qops_model* m, const char* path);
+int32_t qops_model_load(const char* path, qops_model** out);
+int32_t qops_model_free(qops_model* m);
+
+/* Predicted run time of a plan under the pricing of `opts` (PROFILED: the
+ * plain cost table fitted to opts->profile; LEARNED: opts->model). */
+int32_t qops_plan_predict(const qops_plan* p, const qops_plan_opts* opts, double* seconds);
+/* Predicted time of every pass recorded in `pr` (held-out evaluation of a
+ * cost model), out: one double per pass. */
+int32_t qops_profile_predict_passes(const qops_profile* pr, const qops_plan_opts* opts, double* out);
+/* Binary save / load of a profile (pass records, features, counters), the
+ * corpus a plain cost table is fitted to. */
+int32_t qops_profile_save(const qops_profile* pr, const char* path);
+int32_t qops_profile_load(const char* path, qops_profile** out);
+/* An empty profile to merge runs into. */
+int32_t qops_profile_create(int32_t n, qops_profile** out);
 
 /* ------------------------------------------------------------ layout ---- */
 /* SWAP of logical qubits a and b.  VIRTUAL: exchange l2p[a] and l2p[b], move

@@ -33,6 +33,24 @@ def init_params(seed: int) -> Dict[str, np.ndarray]:
     return p
 
 
+def unflatten(flat: np.ndarray) -> Dict[str, np.ndarray]:
+    """Flat parameter vector (W1, b1, W2, b2, W3, b3; W_i out x in) -> dict."""
+    flat = np.asarray(flat, dtype=np.float64)
+    p, o = {}, 0
+    for i in range(3):
+        fi, fo = SIZES[i], SIZES[i + 1]
+        p[f"W{i + 1}"] = flat[o:o + fo * fi].reshape(fo, fi)
+        o += fo * fi
+        p[f"b{i + 1}"] = flat[o:o + fo].copy()
+        o += fo
+    assert o == flat.size
+    return p
+
+
+def flatten(p: Dict[str, np.ndarray]) -> np.ndarray:
+    return np.concatenate([p[f"{k}{i}"].ravel() for i in (1, 2, 3) for k in ("W", "b")])
+
+
 def forward(p: Dict[str, np.ndarray], X: np.ndarray) -> Tuple[np.ndarray, Dict[str, np.ndarray]]:
     X = np.asarray(X, dtype=np.float64)
     z1 = X @ p["W1"].T + p["b1"]

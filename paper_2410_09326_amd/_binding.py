@@ -43,7 +43,7 @@ class Gate(ctypes.Structure):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("swap_mode", ctypes.c_int32), ("tile_upper", ctypes.c_int32),
                 ("max_fuse_k", ctypes.c_int32), ("use_mfma", ctypes.c_int32), ("check_unitary", ctypes.c_int32),
-                ("profile", ctypes.c_void_p), ("model", ctypes.c_void_p)]
+                ("remap", ctypes.c_int32), ("profile", ctypes.c_void_p), ("model", ctypes.c_void_p)]
 
 
 class PlanStats(ctypes.Structure):
@@ -105,6 +105,24 @@ SIGNATURES = {
     "qops_profile_dump": (_I32, [_VP, ctypes.c_char_p]),
     "qops_profile_merge": (_I32, [_VP, _VP]),
     "qops_profile_free": (_I32, [_VP]),
+    "qops_profile_create": (_I32, [_I32, ctypes.POINTER(_VP)]),
+    "qops_profile_save": (_I32, [_VP, ctypes.c_char_p]),
+    "qops_profile_load": (_I32, [ctypes.c_char_p, ctypes.POINTER(_VP)]),
+    "qops_profile_predict_passes": (_I32, [_VP, ctypes.POINTER(PlanOpts), _DP]),
+    "qops_plan_predict": (_I32, [_VP, ctypes.POINTER(PlanOpts), _DP]),
+    "qops_mlp_num_params": (_I32, [ctypes.POINTER(_SZ)]),
+    "qops_mlp_create": (_I32, [ctypes.POINTER(ctypes.c_float), _SZ, ctypes.POINTER(_VP)]),
+    "qops_mlp_set_normalization": (_I32, [_VP, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
+    "qops_mlp_get_params": (_I32, [_VP, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                                   ctypes.POINTER(ctypes.c_float)]),
+    "qops_mlp_grad": (_I32, [_VP, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float), _I32,
+                             ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
+    "qops_mlp_train": (_I32, [_VP, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float), _I32, _I32, _I32,
+                              ctypes.c_float, _U64, ctypes.POINTER(ctypes.c_float)]),
+    "qops_mlp_predict": (_I32, [_VP, ctypes.POINTER(ctypes.c_float), _I32, ctypes.POINTER(ctypes.c_float)]),
+    "qops_model_save": (_I32, [_VP, ctypes.c_char_p]),
+    "qops_model_load": (_I32, [ctypes.c_char_p, ctypes.POINTER(_VP)]),
+    "qops_model_free": (_I32, [_VP]),
     "qops_swap": (_I32, [_VP, _I32, _I32, _I32]),
     "qops_get_layout": (_I32, [_VP, _IP]),
     "qops_set_layout": (_I32, [_VP, _IP]),
@@ -121,6 +139,12 @@ def lib():
     fallback implementation)."""
     global _lib
     if _lib is None:
+        # PyTorch provides the device memory and streams; loading it first makes
+        # the library bind to the same HIP runtime instance (same SONAME).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"libqops.so not found at {LIB_PATH}; build it with "
                               f"`python -m paper_2410_09326_amd.build` (hipcc, gfx950)")
@@ -193,11 +217,11 @@ class GateArray:
 
 
 def plan_opts(mode: int = PLAN_FUSED, swap_mode: int = SWAP_VIRTUAL, tile_upper: int = 0, max_fuse_k: int = 0,
-              use_mfma: int = 1, check_unitary: int = 0, profile=None, model=None) -> PlanOpts:
+              use_mfma: int = 1, check_unitary: int = 0, remap: int = 0, profile=None, model=None) -> PlanOpts:
     o = PlanOpts()
     check(lib().qops_plan_opts_default(ctypes.byref(o)))
     o.mode, o.swap_mode, o.tile_upper = mode, swap_mode, tile_upper
-    o.max_fuse_k, o.use_mfma, o.check_unitary = max_fuse_k, use_mfma, check_unitary
+    o.max_fuse_k, o.use_mfma, o.check_unitary, o.remap = max_fuse_k, use_mfma, check_unitary, remap
     o.profile = profile.handle if profile is not None else None
     o.model = model.handle if model is not None else None
     return o
@@ -269,6 +293,12 @@ class Plan:
             i += 1
         return out
 
+    def predict(self, **opts) -> float:
+        v = ctypes.c_double()
+        o = plan_opts(**opts)
+        check(lib().qops_plan_predict(self.handle, ctypes.byref(o), ctypes.byref(v)))
+        return v.value
+
     def update(self, gates) -> None:
         self._gates = gates if isinstance(gates, GateArray) else GateArray(gates)
         check(lib().qops_plan_update(self.handle, self._gates.ptr(), self._gates.n))
@@ -326,6 +356,112 @@ class Profile:
 
     def merge(self, other: "Profile") -> None:
         check(lib().qops_profile_merge(self.handle, other.handle))
+
+    @classmethod
+    def empty(cls, n: int) -> "Profile":
+        h = ctypes.c_void_p()
+        check(lib().qops_profile_create(n, ctypes.byref(h)))
+        return cls(h)
+
+    def save(self, path: str) -> None:
+        check(lib().qops_profile_save(self.handle, path.encode()))
+
+    @classmethod
+    def load(cls, path: str) -> "Profile":
+        h = ctypes.c_void_p()
+        check(lib().qops_profile_load(path.encode(), ctypes.byref(h)))
+        return cls(h)
+
+    def predict_passes(self, **opts) -> np.ndarray:
+        """Cost-model prediction (seconds) for every pass recorded here."""
+        n = ctypes.c_size_t()
+        check(lib().qops_profile_num_passes(self.handle, ctypes.byref(n)))
+        out = np.zeros(n.value, dtype=np.float64)
+        o = plan_opts(**opts)
+        check(lib().qops_profile_predict_passes(self.handle, ctypes.byref(o), out.ctypes.data_as(_DP)))
+        return out
+
+
+_FP = ctypes.POINTER(ctypes.c_float)
+
+
+def _f32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+class CostModel:
+    """The learned pass-time model (64 -> 128 -> 128 -> 1 perceptron) whose
+    training, gradients and predictions run in the library's GPU kernels."""
+
+    NFEAT = 64
+
+    def __init__(self, params: Optional[np.ndarray] = None, handle=None) -> None:
+        if handle is not None:
+            self.handle = handle
+            return
+        h = ctypes.c_void_p()
+        if params is None:
+            check(lib().qops_mlp_create(None, 0, ctypes.byref(h)))
+        else:
+            p = _f32(params)
+            check(lib().qops_mlp_create(p.ctypes.data_as(_FP), p.size, ctypes.byref(h)))
+        self.handle = h
+
+    @staticmethod
+    def num_params() -> int:
+        n = ctypes.c_size_t()
+        check(lib().qops_mlp_num_params(ctypes.byref(n)))
+        return n.value
+
+    @classmethod
+    def load(cls, path: str) -> "CostModel":
+        h = ctypes.c_void_p()
+        check(lib().qops_model_load(path.encode(), ctypes.byref(h)))
+        return cls(handle=h)
+
+    def save(self, path: str) -> None:
+        check(lib().qops_model_save(self.handle, path.encode()))
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                lib().qops_model_free(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+    def set_normalization(self, mu, sd) -> None:
+        m, s = _f32(mu), _f32(sd)
+        check(lib().qops_mlp_set_normalization(self.handle, m.ctypes.data_as(_FP), s.ctypes.data_as(_FP)))
+
+    def params(self):
+        p = np.zeros(self.num_params(), dtype=np.float32)
+        mu = np.zeros(self.NFEAT, dtype=np.float32)
+        sd = np.zeros(self.NFEAT, dtype=np.float32)
+        check(lib().qops_mlp_get_params(self.handle, p.ctypes.data_as(_FP), mu.ctypes.data_as(_FP),
+                                        sd.ctypes.data_as(_FP)))
+        return p, mu, sd
+
+    def grad(self, X, t):
+        X, t = _f32(X), _f32(t)
+        g = np.zeros(self.num_params(), dtype=np.float32)
+        loss = ctypes.c_float()
+        check(lib().qops_mlp_grad(self.handle, X.ctypes.data_as(_FP), t.ctypes.data_as(_FP), len(t),
+                                  g.ctypes.data_as(_FP), ctypes.byref(loss)))
+        return float(loss.value), g
+
+    def train(self, X, t, epochs: int = 20, batch: int = 256, lr: float = 1e-3, seed: int = 0) -> float:
+        X, t = _f32(X), _f32(t)
+        loss = ctypes.c_float()
+        check(lib().qops_mlp_train(self.handle, X.ctypes.data_as(_FP), t.ctypes.data_as(_FP), len(t), epochs, batch,
+                                   float(lr), int(seed), ctypes.byref(loss)))
+        return float(loss.value)
+
+    def predict(self, X) -> np.ndarray:
+        X = _f32(X)
+        out = np.zeros(X.shape[0], dtype=np.float32)
+        check(lib().qops_mlp_predict(self.handle, X.ctypes.data_as(_FP), X.shape[0], out.ctypes.data_as(_FP)))
+        return out
 
 
 # ---------------------------------------------------------------------------

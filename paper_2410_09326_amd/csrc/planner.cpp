@@ -929,6 +929,45 @@ Err build_plan(int n, int prec, const int32_t* l2p_in, const qops_gate* g, size_
         }
     std::vector<int> l2p = p.l2p_in;
     std::vector<LOp> lowered;
+    if (par.remap && n > 6 && par.mode != QOPS_PLAN_GATEWISE) {
+        // Profile-guided remap (virtual swap, paper Sec. III-D): the qubits
+        // that non-diagonal gates target most often are moved into physical
+        // bits 0..5, which every tile pass holds, by bit exchanges up front.
+        std::vector<long> hits(n, 0);
+        for (size_t i = 0; i < ng; ++i) {
+            const qops_gate& g = p.gates[i];
+            if (diag_kind(g.kind) || g.kind == QOPS_SWAP) continue;
+            const int k = g.kind == QOPS_DENSE ? g.k : gate_arity(g.kind);
+            if (g.kind == QOPS_CX) hits[g.q[1]]++;
+            else
+                for (int j = 0; j < k; ++j) hits[g.q[j]]++;
+        }
+        std::vector<int> order(n);
+        for (int q = 0; q < n; ++q) order[q] = q;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return hits[a] > hits[b]; });
+        std::vector<bool> hot(n, false);
+        for (int i = 0; i < 6; ++i) hot[order[i]] = hits[order[i]] > 0;
+        std::vector<int> p2l(n);
+        for (int q = 0; q < n; ++q) p2l[l2p[q]] = q;
+        for (int i = 0; i < 6; ++i) {
+            const int q = order[i];
+            if (!hot[q] || l2p[q] < 6) continue;
+            int slot = -1;
+            for (int b = 0; b < 6 && slot < 0; ++b)
+                if (!hot[p2l[b]]) slot = b;
+            if (slot < 0) break;
+            LOp o;
+            o.kind = LOp::PSWAP;
+            o.k = 2;
+            o.t[0] = slot;
+            o.t[1] = l2p[q];
+            lowered.push_back(o);
+            const int other = p2l[slot];
+            std::swap(l2p[q], l2p[other]);
+            p2l[l2p[q]] = q;
+            p2l[l2p[other]] = other;
+        }
+    }
     e = lower(n, p.gates.data(), ng, par.swap_mode, l2p, lowered, p.n_virtual_swaps);
     if (!e.ok()) return e;
     p.l2p_out = l2p;

@@ -52,6 +52,7 @@ struct PlanParams {
     int use_mfma = 1;
     int state_lds_max_n = 12;  // whole state in one work-group's LDS up to this n
     int check_unitary = 0;
+    int remap = 0;             // move the most-targeted qubits into physical bits 0..5 first
 };
 
 struct Plan {

@@ -198,6 +198,60 @@ int32_t qops_profile_merge(qops_profile* dst, const qops_profile* src)
     return QOPS_OK;
 }
 
+int32_t qops_profile_create(int32_t n, qops_profile** out)
+{
+    if (!out || n < 1 || n > QOPS_MAX_QUBITS) return set_error(QOPS_INVALID_ARG, "bad arguments");
+    qops_profile* p = new qops_profile();
+    p->n = n;
+    p->lcount.assign((size_t)QOPS_NUM_KINDS * n, 0);
+    p->pcount.assign((size_t)QOPS_NUM_KINDS * n, 0);
+    *out = p;
+    return QOPS_OK;
+}
+
+int32_t qops_profile_save(const qops_profile* pr, const char* path)
+{
+    if (!pr || !path) return set_error(QOPS_INVALID_ARG, "null argument");
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return set_error(QOPS_INVALID_ARG, std::string("cannot open ") + path);
+    const char magic[8] = {'Q', 'O', 'P', 'S', 'P', 'R', 'F', '1'};
+    const uint64_t nr = pr->recs.size(), nc = pr->lcount.size();
+    bool ok = std::fwrite(magic, 1, 8, f) == 8 && std::fwrite(&pr->n, 4, 1, f) == 1 && std::fwrite(&pr->prec, 4, 1, f) == 1 &&
+              std::fwrite(&pr->total, 8, 1, f) == 1 && std::fwrite(&nr, 8, 1, f) == 1 && std::fwrite(&nc, 8, 1, f) == 1 &&
+              std::fwrite(pr->recs.data(), sizeof(qops_pass_record), nr, f) == nr &&
+              std::fwrite(pr->feats.data(), sizeof(float), nr * kNumFeatures, f) == nr * kNumFeatures &&
+              std::fwrite(pr->lcount.data(), 4, nc, f) == nc && std::fwrite(pr->pcount.data(), 4, nc, f) == nc;
+    std::fclose(f);
+    return ok ? QOPS_OK : set_error(QOPS_INVALID_ARG, "write failed");
+}
+
+int32_t qops_profile_load(const char* path, qops_profile** out)
+{
+    if (!path || !out) return set_error(QOPS_INVALID_ARG, "null argument");
+    *out = nullptr;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return set_error(QOPS_INVALID_ARG, std::string("cannot open ") + path);
+    std::unique_ptr<qops_profile> p(new qops_profile());
+    char magic[8];
+    uint64_t nr = 0, nc = 0;
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "QOPSPRF1", 8) == 0 &&
+              std::fread(&p->n, 4, 1, f) == 1 && std::fread(&p->prec, 4, 1, f) == 1 && std::fread(&p->total, 8, 1, f) == 1 &&
+              std::fread(&nr, 8, 1, f) == 1 && std::fread(&nc, 8, 1, f) == 1 && nr < (1ull << 28) && nc < (1ull << 20);
+    if (ok) {
+        p->recs.resize(nr);
+        p->feats.resize(nr * kNumFeatures);
+        p->lcount.resize(nc);
+        p->pcount.resize(nc);
+        ok = std::fread(p->recs.data(), sizeof(qops_pass_record), nr, f) == nr &&
+             std::fread(p->feats.data(), sizeof(float), nr * kNumFeatures, f) == nr * kNumFeatures &&
+             std::fread(p->lcount.data(), 4, nc, f) == nc && std::fread(p->pcount.data(), 4, nc, f) == nc;
+    }
+    std::fclose(f);
+    if (!ok) return set_error(QOPS_INVALID_ARG, "not a qops profile file");
+    *out = p.release();
+    return QOPS_OK;
+}
+
 int32_t qops_profile_free(qops_profile* pr)
 {
     delete pr;

@@ -163,6 +163,7 @@ PlanParams params_from(const qops_plan_opts* o, int n, int prec)
         par.L_lds = std::min(6 + o->tile_upper, prec == QOPS_C64 ? 13 : 12);
     }
     par.max_fuse_k = o->max_fuse_k > 0 ? o->max_fuse_k : 1;
+    par.remap = o->remap;
     par.use_mfma = o->use_mfma;
     par.check_unitary = o->check_unitary;
     (void)n;

@@ -100,6 +100,12 @@ def test_plan_ops_reproduce_circuit(name, make, mode, swap_mode):
     assert np.max(np.abs(got - ref)) <= 1e-12
     exp_l2p = orc.expected_layout(c.n, c.gates, virtual_swaps=(swap_mode == q.SWAP_VIRTUAL))
     assert np.array_equal(plan.final_layout(), exp_l2p)
+    if mode == q.PLAN_FUSED and swap_mode == q.SWAP_VIRTUAL:
+        # with the up-front remap the result is the same state; the layout it
+        # ends in is the remap followed by the circuit's virtual swaps
+        rp = q.Plan(c.n, c.gates, precision=q.C128, remap=1)
+        got2 = physical_replay(c.n, rp, c.x0)
+        assert np.max(np.abs(got2 - ref)) <= 1e-12
     st = plan.stats()
     if swap_mode == q.SWAP_VIRTUAL:
         assert st["n_virtual_swaps"] == sum(1 for g in c.gates if g.kind == "swap")

@@ -289,5 +289,19 @@ def param_sweep_batch(seed: int = 5, count: int = 512, nmin: int = 10, nmax: int
     return out
 
 
+def mlp_init(seed: int, sizes: Sequence[int] = (64, 128, 128, 1)) -> np.ndarray:
+    """Seeded He-uniform initial weights of the cost-model perceptron, flat
+    float64 in the order W1, b1, W2, b2, W3, b3 (W_i is out x in, row-major;
+    biases start at zero)."""
+    rng = rng_for(seed)
+    parts = []
+    for i in range(len(sizes) - 1):
+        fan_in, fan_out = sizes[i], sizes[i + 1]
+        lim = np.sqrt(6.0 / fan_in)
+        parts.append(rng.uniform(-lim, lim, size=fan_out * fan_in))
+        parts.append(np.zeros(fan_out))
+    return np.concatenate(parts)
+
+
 def swap_positions(c: Circuit) -> List[int]:
     return [i for i, g in enumerate(c.gates) if g.kind == "swap"]
