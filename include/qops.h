@@ -309,6 +309,57 @@ int32_t qops_profile_load(const char* path, qops_profile** out);
 /* An empty profile to merge runs into. */
 int32_t qops_profile_create(int32_t n, qops_profile** out);
 
+/* --------------------------------------------------- batched runs ---- */
+/* Many small, uneven circuits (a parameter sweep, paper Sec. IV-E: the same
+ * ansatz simulated again and again with new angles) run as ONE graph launch:
+ * circuits of up to small_max_n qubits each run start to finish in one
+ * work-group's LDS; the larger ones are planned into tile passes and graph
+ * node p runs pass p of every circuit that has one.  Every circuit starts in
+ * |0..0>; the outputs are <Z_q> of every logical qubit of every circuit
+ * (FP64, deterministic), concatenated in circuit order (sum of n_i doubles).
+ * SWAP gates are handled virtually. */
+typedef struct qops_batch {
+    int32_t count;                 /* circuits                                  */
+    const int32_t* n;              /* qubits of each circuit (1..26)            */
+    const qops_gate* const* gates; /* gate list of each circuit                 */
+    const size_t* n_gates;
+    int32_t precision;             /* QOPS_C64 / QOPS_C128                      */
+    void* stream;                  /* hipStream_t; null = a private stream      */
+    int32_t small_max_n;           /* whole-state-in-LDS limit (0 = 13 / 12)    */
+    int32_t tile_bits;             /* tile size 2^tile_bits of the larger ones
+                                      (0 = 13 / 12)                             */
+} qops_batch;
+typedef struct qops_batch_exec qops_batch_exec;
+typedef struct qops_batch_stats {
+    int32_t small_circuits;
+    int32_t tile_circuits;
+    int32_t graph_nodes;
+    int32_t small_max_n;
+    int32_t tile_bits;
+    int64_t outputs;
+    double state_bytes;            /* device memory of the tile-pass states     */
+} qops_batch_stats;
+/* Plans every circuit, lays out the device program, runs the batch once and
+ * captures it as a graph.  Gate lists are copied. */
+int32_t qops_batch_create(const qops_batch* b, qops_batch_exec** out);
+/* One graph launch (asynchronous). */
+int32_t qops_batch_launch(qops_batch_exec* e);
+/* Waits and copies the <Z> outputs (sum of n_i doubles). */
+int32_t qops_batch_results(qops_batch_exec* e, double* out_expz);
+/* Mean device time of `reps` back-to-back graph launches (blocking). */
+int32_t qops_batch_time(qops_batch_exec* e, int32_t reps, double* seconds);
+/* New angles / matrices for every circuit (same structure): re-composes the
+ * fused operations in FP64 and replaces the coefficients the graph reads;
+ * QOPS_BAD_STATE if the structure changed. */
+int32_t qops_batch_update(qops_batch_exec* e, const qops_gate* const* gates, const size_t* n_gates);
+int32_t qops_batch_info(const qops_batch_exec* e, qops_batch_stats* s);
+int32_t qops_batch_free(qops_batch_exec* e);
+/* Autotuner: times the batch for every (small_max_n, tile_bits) candidate
+ * and returns the fastest; results are cached in a text file keyed by the
+ * batch's precision, size and qubit-count histogram (cache_path nullable). */
+int32_t qops_batch_autotune(const qops_batch* b, const char* cache_path, int32_t* best_small_max_n,
+                            int32_t* best_tile_bits, double* best_seconds);
+
 /* ------------------------------------------------------------ layout ---- */
 /* SWAP of logical qubits a and b.  VIRTUAL: exchange l2p[a] and l2p[b], move
  * no amplitude.  PHYSICAL: one bit-exchange pass over the state. */

@@ -66,6 +66,19 @@ class OpInfo(ctypes.Structure):
                 ("cmask", ctypes.c_uint64), ("pass_", ctypes.c_int32), ("n_merged", ctypes.c_int32)]
 
 
+class BatchDesc(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("n", ctypes.POINTER(ctypes.c_int32)),
+                ("gates", ctypes.POINTER(ctypes.POINTER(Gate))), ("n_gates", ctypes.POINTER(ctypes.c_size_t)),
+                ("precision", ctypes.c_int32), ("stream", ctypes.c_void_p), ("small_max_n", ctypes.c_int32),
+                ("tile_bits", ctypes.c_int32)]
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("small_circuits", ctypes.c_int32), ("tile_circuits", ctypes.c_int32),
+                ("graph_nodes", ctypes.c_int32), ("small_max_n", ctypes.c_int32), ("tile_bits", ctypes.c_int32),
+                ("outputs", ctypes.c_int64), ("state_bytes", ctypes.c_double)]
+
+
 class PassInfo(ctypes.Structure):
     _fields_ = [("type", ctypes.c_int32), ("tile_bits", ctypes.c_int32), ("n_upper", ctypes.c_int32),
                 ("upper", ctypes.c_int32 * 8), ("n_ops", ctypes.c_int32), ("n_remaps", ctypes.c_int32),
@@ -123,6 +136,14 @@ SIGNATURES = {
     "qops_model_save": (_I32, [_VP, ctypes.c_char_p]),
     "qops_model_load": (_I32, [ctypes.c_char_p, ctypes.POINTER(_VP)]),
     "qops_model_free": (_I32, [_VP]),
+    "qops_batch_create": (_I32, [ctypes.POINTER(BatchDesc), ctypes.POINTER(_VP)]),
+    "qops_batch_launch": (_I32, [_VP]),
+    "qops_batch_results": (_I32, [_VP, _DP]),
+    "qops_batch_time": (_I32, [_VP, _I32, _DP]),
+    "qops_batch_update": (_I32, [_VP, ctypes.POINTER(ctypes.POINTER(Gate)), ctypes.POINTER(ctypes.c_size_t)]),
+    "qops_batch_info": (_I32, [_VP, ctypes.POINTER(BatchStats)]),
+    "qops_batch_free": (_I32, [_VP]),
+    "qops_batch_autotune": (_I32, [ctypes.POINTER(BatchDesc), ctypes.c_char_p, _IP, _IP, _DP]),
     "qops_swap": (_I32, [_VP, _I32, _I32, _I32]),
     "qops_get_layout": (_I32, [_VP, _IP]),
     "qops_set_layout": (_I32, [_VP, _IP]),
@@ -462,6 +483,77 @@ class CostModel:
         out = np.zeros(X.shape[0], dtype=np.float32)
         check(lib().qops_mlp_predict(self.handle, X.ctypes.data_as(_FP), X.shape[0], out.ctypes.data_as(_FP)))
         return out
+
+
+class Batch:
+    """Many circuits (each given as (n, gates)) simulated from |0..0> in one
+    graph launch; results are <Z_q> per circuit."""
+
+    def __init__(self, circuits, precision: int = C64, small_max_n: int = 0, tile_bits: int = 0) -> None:
+        self.ns = [int(n) for n, _ in circuits]
+        self._desc, self._keep = self._describe(circuits, precision, small_max_n, tile_bits)
+        h = ctypes.c_void_p()
+        check(lib().qops_batch_create(ctypes.byref(self._desc), ctypes.byref(h)))
+        self.handle = h
+
+    @staticmethod
+    def _describe(circuits, precision, small_max_n, tile_bits):
+        arrays = [g if isinstance(g, GateArray) else GateArray(g) for _, g in circuits]
+        cnt = len(arrays)
+        ns = (ctypes.c_int32 * cnt)(*[int(n) for n, _ in circuits])
+        gp = (ctypes.POINTER(Gate) * cnt)(*[a.ptr() for a in arrays])
+        ng = (ctypes.c_size_t * cnt)(*[a.n for a in arrays])
+        d = BatchDesc(cnt, ns, gp, ng, precision, None, small_max_n, tile_bits)
+        return d, (arrays, ns, gp, ng)
+
+    @staticmethod
+    def autotune(circuits, precision: int = C64, cache: Optional[str] = None):
+        d, keep = Batch._describe(circuits, precision, 0, 0)
+        sm, tb, sec = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        check(lib().qops_batch_autotune(ctypes.byref(d), cache.encode() if cache else None, ctypes.byref(sm),
+                                        ctypes.byref(tb), ctypes.byref(sec)))
+        return sm.value, tb.value, sec.value
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            lib().qops_batch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def launch(self) -> None:
+        check(lib().qops_batch_launch(self.handle))
+
+    def results(self) -> List[np.ndarray]:
+        out = np.zeros(sum(self.ns), dtype=np.float64)
+        check(lib().qops_batch_results(self.handle, out.ctypes.data_as(_DP)))
+        res, o = [], 0
+        for n in self.ns:
+            res.append(out[o:o + n].copy())
+            o += n
+        return res
+
+    def time(self, reps: int = 5) -> float:
+        v = ctypes.c_double()
+        check(lib().qops_batch_time(self.handle, reps, ctypes.byref(v)))
+        return v.value
+
+    def update(self, gate_lists) -> None:
+        arrays = [g if isinstance(g, GateArray) else GateArray(g) for g in gate_lists]
+        cnt = len(arrays)
+        gp = (ctypes.POINTER(Gate) * cnt)(*[a.ptr() for a in arrays])
+        ng = (ctypes.c_size_t * cnt)(*[a.n for a in arrays])
+        check(lib().qops_batch_update(self.handle, gp, ng))
+        self._upd = (arrays, gp, ng)
+
+    def info(self) -> dict:
+        s = BatchStats()
+        check(lib().qops_batch_info(self.handle, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in BatchStats._fields_}
 
 
 # ---------------------------------------------------------------------------

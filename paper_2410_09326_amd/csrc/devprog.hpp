@@ -67,6 +67,23 @@ struct PassHdr {
     int32_t pad[1];
 };
 
+// Batched executor records.
+struct BatchCirc {
+    void* state;        // circuits run in tile passes: their state buffer
+    int32_t n;
+    int32_t npass;      // tile passes
+    int32_t hdr0;       // first pass header in the batch's header array
+    int32_t out0;       // offset of the circuit's n <Z> outputs
+    int32_t op0;        // whole-state circuits: their operations
+    int32_t nops;
+    int32_t part0;      // first partial-sum record of the <Z> reduction
+    int32_t pad;
+};
+struct BatchItem {
+    int32_t c;          // circuit
+    int32_t tile;       // tile (pass kernels) or chunk (reduction)
+};
+
 // A mapping assigns the upper tile positions to register bits (first R
 // nibbles) and wave bits (next W nibbles).
 __host__ __device__ inline int32_t map_get(uint32_t m, int i) { return (int32_t)((m >> (4 * i)) & 15u); }

@@ -896,7 +896,7 @@ hipError_t launch_tile_lds(int prec, void* state, const PassHdr* hdr, const DevO
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__device__ void run_ops_lds(typename CxT<T>::V* lds, int n, const DevOp* __restrict__ ops, int nops,
+__device__ __forceinline__ void run_ops_lds(typename CxT<T>::V* lds, int n, const DevOp* __restrict__ ops, int nops,
                            const T* __restrict__ coef, int tid, int nthr)
 {
     const int lane = tid & 63, wave = tid >> 6;
@@ -1453,5 +1453,235 @@ hipError_t launch_gather_logical(int prec, const void* state, int n, const int* 
                            reinterpret_cast<const double2*>(state), n, pa, x0, count, reinterpret_cast<double2*>(dst));
     return hipGetLastError();
 }
+
+
+// ---------------------------------------------------------------------------
+// Batched executor (many small circuits, one graph launch)
+// ---------------------------------------------------------------------------
+
+// Fixed-order sum over the 256 threads of a block of v; every thread gets it.
+__device__ __forceinline__ double bsum(double v, double* sh)
+{
+    return block_sum_256(v, sh);
+}
+
+// One work-group per circuit whose whole state fits in LDS: |0..0>, every
+// operation, then <Z_q> = sum p - 2 sum_{x: bit q} p, reduced in FP64.
+template <typename T>
+__global__ void __launch_bounds__(256)
+batch_small_kernel(const int32_t* __restrict__ ids, const BatchCirc* __restrict__ circs, const DevOp* __restrict__ ops,
+                   const T* __restrict__ coef, double* __restrict__ out)
+{
+    using V = typename CxT<T>::V;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double sh[256];
+    V* lds = reinterpret_cast<V*>(smem_raw);
+    const BatchCirc c = circs[ids[blockIdx.x]];
+    const int n = c.n;
+    const uint32_t N = 1u << n;
+    const int tid = threadIdx.x;
+    for (uint32_t x = tid; x < N; x += 256) {
+        V v;
+        v.x = x == 0 ? (T)1 : (T)0;
+        v.y = 0;
+        lds[swz(x)] = v;
+    }
+    __syncthreads();
+    run_ops_lds<T>(lds, n, ops + c.op0, c.nops, coef, tid, 256);
+    // one sweep over the LDS state per output (q = -1: the total)
+    double all = 0.0;
+    for (int q = -1; q < n; ++q) {
+        double acc = 0.0;
+        for (uint32_t x = tid; x < N; x += 256) {
+            if (q >= 0 && !((x >> q) & 1u)) continue;
+            const V v = lds[swz(x)];
+            acc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+        }
+        const double s = bsum(acc, sh);
+        if (q < 0) all = s;
+        else if (tid == 0) out[c.out0 + q] = all - 2.0 * s;
+    }
+}
+
+// Pass `pass` of every circuit that has one: grid-stride over its tiles.
+// Pass 0 starts from |0..0> instead of reading the state.
+template <typename T>
+__global__ void __launch_bounds__(256)
+batch_pass_kernel(const BatchItem* __restrict__ items, int nitems, const BatchCirc* __restrict__ circs,
+                  const PassHdr* __restrict__ hdrs, const DevOp* __restrict__ ops, const T* __restrict__ coef, int pass)
+{
+    using V = typename CxT<T>::V;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    V* lds = reinterpret_cast<V*>(smem_raw);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+        const BatchItem it = items[i];
+        const BatchCirc c = circs[it.c];
+        const PassHdr* __restrict__ hp = hdrs + c.hdr0 + pass;
+        V* __restrict__ st = reinterpret_cast<V*>(c.state);
+        const int L = hp->L, nup = hp->nup;
+        const uint32_t N = 1u << L;
+        const uint64_t base = tile_base((uint64_t)it.tile, hp);
+        for (uint32_t e = tid; e < N; e += 256) {
+            V v;
+            if (pass == 0) {
+                v.x = (base == 0 && e == 0) ? (T)1 : (T)0;
+                v.y = 0;
+            } else {
+                v = st[base + (e & 63u) + dep_up(e >> 6, hp->up_phys, nup)];
+            }
+            lds[swz(e)] = v;
+        }
+        __syncthreads();
+        const DevOp* __restrict__ prog = ops + hp->op0;
+        for (int j = 0; j < hp->nops; ++j) {
+            const DevOp op = prog[j];
+            if ((base & op.c_glob) != op.c_glob) continue;
+            const T* cf = op.b ? coef + hp->coef_src + op.coef : coef + op.coef;
+            if (op.type == OP_DENSE_LDS)
+                dense_lds_dispatch<T>(lds, L, op, coef + op.coef, tid, 256);
+            else if (op.type == OP_MFMA)
+                mfma_dispatch<T>(lds, L, op, cf, lane, wave);
+            else if (op.type == OP_DIAG_LDS)
+                diag_lds<T>(lds, L, op, cf, base, tid, 256);
+            __syncthreads();
+        }
+        for (uint32_t e = tid; e < N; e += 256) st[base + (e & 63u) + dep_up(e >> 6, hp->up_phys, nup)] = lds[swz(e)];
+        __syncthreads();
+    }
+}
+
+// <Z> partial sums of the tile-pass circuits: item = (circuit, chunk of
+// 2^s amplitudes, s = min(n, 13)); record (n+1 of QOPS_BATCH_REC doubles):
+// sum p, sum p bit_q.
+template <typename T>
+__global__ void __launch_bounds__(256)
+batch_zpart_kernel(const BatchItem* __restrict__ items, int nitems, const BatchCirc* __restrict__ circs,
+                   double* __restrict__ part)
+{
+    using V = typename CxT<T>::V;
+    __shared__ double sh[256];
+    const int t = threadIdx.x;
+    for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+        const BatchItem it = items[i];
+        const BatchCirc c = circs[it.c];
+        const int n = c.n, s = n < 13 ? n : 13;
+        const V* __restrict__ st = reinterpret_cast<const V*>(c.state);
+        const uint64_t base = (uint64_t)it.tile << s;
+        double tot = 0.0, sb[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) sb[q] = 0.0;
+        for (uint32_t j = 0; (j << 8) < (1u << s); ++j) {
+            const uint32_t off = (j << 8) + t;
+            if (off >= (1u << s)) break;
+            double p;
+            if (c.npass == 0) {
+                p = (base + off == 0) ? 1.0 : 0.0;     // no gates: still |0..0>
+            } else {
+                const V v = st[base + off];
+                p = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+            }
+            tot += p;
+#pragma unroll
+            for (int q = 0; q < 5; ++q)
+                if ((j >> q) & 1u) sb[q] += p;
+        }
+        double* rec = part + (size_t)(c.part0 + it.tile) * QOPS_BATCH_REC;
+        const double all = bsum(tot, sh);
+        if (t == 0) rec[0] = all;
+        for (int q = 0; q < n; ++q) {
+            double v;
+            if (q < 8 && q < s) {
+                v = bsum(((t >> q) & 1) ? tot : 0.0, sh);
+            } else if (q < s) {
+                double mine = 0.0;
+#pragma unroll
+                for (int r = 0; r < 5; ++r)
+                    if (r == q - 8) mine = sb[r];
+                v = bsum(mine, sh);
+            } else {
+                v = ((base >> q) & 1ull) ? all : 0.0;
+            }
+            if (t == 0) rec[1 + q] = v;
+        }
+    }
+}
+
+// One work-group per tile-pass circuit: <Z_q> from its partial records, in
+// chunk order.
+__global__ void __launch_bounds__(256)
+batch_zfinal_kernel(const int32_t* __restrict__ ids, const BatchCirc* __restrict__ circs,
+                    const double* __restrict__ part, double* __restrict__ out)
+{
+    __shared__ double sh[256];
+    const BatchCirc c = circs[ids[blockIdx.x]];
+    const int n = c.n, s = n < 13 ? n : 13;
+    const int nch = 1 << (n - s);
+    double tot = 0.0;
+    for (int k = threadIdx.x; k < nch; k += 256) tot += part[(size_t)(c.part0 + k) * QOPS_BATCH_REC];
+    const double all = bsum(tot, sh);
+    for (int q = 0; q < n; ++q) {
+        double v = 0.0;
+        for (int k = threadIdx.x; k < nch; k += 256) v += part[(size_t)(c.part0 + k) * QOPS_BATCH_REC + 1 + q];
+        const double sq = bsum(v, sh);
+        if (threadIdx.x == 0) out[c.out0 + q] = all - 2.0 * sq;
+    }
+}
+
+hipError_t launch_batch_small(int prec, const int32_t* ids, int count, const BatchCirc* circs, const DevOp* ops,
+                              const void* coef, double* out, int lds_bytes, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    if (prec == 0) {
+        if (hipError_t e = hipFuncSetAttribute((const void*)batch_small_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               lds_bytes))
+            return e;
+        hipLaunchKernelGGL(batch_small_kernel<float>, dim3(count), dim3(256), lds_bytes, s, ids, circs, ops,
+                           reinterpret_cast<const float*>(coef), out);
+    } else {
+        if (hipError_t e = hipFuncSetAttribute((const void*)batch_small_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               lds_bytes))
+            return e;
+        hipLaunchKernelGGL(batch_small_kernel<double>, dim3(count), dim3(256), lds_bytes, s, ids, circs, ops,
+                           reinterpret_cast<const double*>(coef), out);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_pass(int prec, const BatchItem* items, int nitems, const BatchCirc* circs, const PassHdr* hdrs,
+                             const DevOp* ops, const void* coef, int pass, int lds_bytes, int grid, hipStream_t s)
+{
+    if (nitems <= 0) return hipSuccess;
+    const int g = std::max(1, std::min(nitems, grid));
+    if (prec == 0) {
+        if (hipError_t e = hipFuncSetAttribute((const void*)batch_pass_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               lds_bytes))
+            return e;
+        hipLaunchKernelGGL(batch_pass_kernel<float>, dim3(g), dim3(256), lds_bytes, s, items, nitems, circs, hdrs, ops,
+                           reinterpret_cast<const float*>(coef), pass);
+    } else {
+        if (hipError_t e = hipFuncSetAttribute((const void*)batch_pass_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               lds_bytes))
+            return e;
+        hipLaunchKernelGGL(batch_pass_kernel<double>, dim3(g), dim3(256), lds_bytes, s, items, nitems, circs, hdrs, ops,
+                           reinterpret_cast<const double*>(coef), pass);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_z(int prec, const BatchItem* items, int nitems, const int32_t* ids, int count,
+                          const BatchCirc* circs, double* part, double* out, int grid, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    const int g = std::max(1, std::min(nitems, grid));
+    if (prec == 0)
+        hipLaunchKernelGGL(batch_zpart_kernel<float>, dim3(g), dim3(256), 0, s, items, nitems, circs, part);
+    else
+        hipLaunchKernelGGL(batch_zpart_kernel<double>, dim3(g), dim3(256), 0, s, items, nitems, circs, part);
+    hipLaunchKernelGGL(batch_zfinal_kernel, dim3(count), dim3(256), 0, s, ids, circs, part, out);
+    return hipGetLastError();
+}
+
+int device_cus() { return num_cus(); }
 
 }  // namespace qops

@@ -55,4 +55,15 @@ hipError_t launch_probs(int prec, const void* state, int n, int m, const int* po
 hipError_t launch_gather_logical(int prec, const void* state, int n, const int* l2p, uint64_t x0,
                                  uint64_t count, void* dst, hipStream_t s);
 
+// Batched executor kernels.
+#define QOPS_BATCH_SMALL_MAX 13
+#define QOPS_BATCH_REC 32   // doubles per <Z> partial record (n + 1 <= 27)
+hipError_t launch_batch_small(int prec, const int32_t* ids, int count, const BatchCirc* circs, const DevOp* ops,
+                              const void* coef, double* out, int lds_bytes, hipStream_t s);
+hipError_t launch_batch_pass(int prec, const BatchItem* items, int nitems, const BatchCirc* circs, const PassHdr* hdrs,
+                             const DevOp* ops, const void* coef, int pass, int lds_bytes, int grid, hipStream_t s);
+hipError_t launch_batch_z(int prec, const BatchItem* items, int nitems, const int32_t* ids, int count,
+                          const BatchCirc* circs, double* part, double* out, int grid, hipStream_t s);
+int device_cus();
+
 }  // namespace qops

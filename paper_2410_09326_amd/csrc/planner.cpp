@@ -874,7 +874,7 @@ static void pack(Plan& p)
         if (o.kind != LOp::DIAG)
             for (int j = 0; j < o.k; ++j)
                 if (o.t[j] >= 6) need |= 1ull << o.t[j];
-        const bool d2 = dense || o.kind == LOp::DENSE;
+        const bool d2 = dense || o.kind == LOp::DENSE || p.par.force_lds;
         const int cap = d2 ? cap_lds : cap_reg;
         // an LDS pass also keeps its matrix-core fragments next to the tile
         const size_t sb = staged_bytes(p, o, 6 + cap_lds);
@@ -884,7 +884,7 @@ static void pack(Plan& p)
             flush();
             cur.lop.push_back((int)i);
             S = need;
-            dense = o.kind == LOp::DENSE;
+            dense = o.kind == LOp::DENSE || p.par.force_lds;
             staged = sb;
         } else {
             cur.lop.push_back((int)i);

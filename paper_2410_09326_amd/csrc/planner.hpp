@@ -53,6 +53,7 @@ struct PlanParams {
     int state_lds_max_n = 12;  // whole state in one work-group's LDS up to this n
     int check_unitary = 0;
     int remap = 0;             // move the most-targeted qubits into physical bits 0..5 first
+    int force_lds = 0;         // every tile pass is an LDS pass (batched executor)
 };
 
 struct Plan {
