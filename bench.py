@@ -149,6 +149,50 @@ def learned_vs_plain(n_circ: int):
             "corpus_passes": summ["passes"], "circuits": detail}
 
 
+def batch_sweep(reps: int):
+    """The parameter-sweep batch: 512 circuits of 10..22 qubits (RY/RZ layers
+    plus a CZ ladder, depth 8..32, seed 5) in complex64, all in one graph
+    launch producing <Z_i> for every qubit of every circuit.  The autotuner
+    picks the whole-state-in-LDS cut-off and the tile width first.  A sample
+    of eight circuits is re-run one at a time in complex128 on the
+    single-circuit path to state the batch's max-abs error."""
+    import tempfile
+    import numpy as np
+    import paper_2410_09326_amd as q
+    from workloads import circuits as W
+    circs = W.param_sweep_batch(5)
+    spec = [(c.n, q.GateArray(c.gates)) for c in circs]
+    cache = os.path.join(tempfile.gettempdir(), "qops_batch_tune.txt")
+    t0 = time.perf_counter()
+    sm, tb, _ = q.Batch.autotune(spec, precision=q.C64, cache=cache)
+    tune_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    b = q.Batch(spec, precision=q.C64, small_max_n=sm, tile_bits=tb)
+    create_s = time.perf_counter() - t0
+    info = b.info()
+    b.launch()
+    res = b.results()
+    sec = b.time(reps)
+    b.close()
+    err = 0.0
+    pick = np.linspace(0, len(circs) - 1, 8).astype(int)
+    for i in pick:
+        c = circs[i]
+        sim = q.Simulator(c.n, q.C128)
+        sim.init_basis(0)
+        sim.run(q.Plan(c.n, spec[i][1], precision=q.C128))
+        err = max(err, float(np.max(np.abs(sim.expect_z() - res[i]))))
+        sim.close()
+    return {"workload": "512 parameterised circuits, n~U{10..22}, RY/RZ layers + CZ ladder, depth U{8..32} "
+                        "(seed 5), complex64, one graph launch, <Z_i> of every qubit",
+            "circuits_per_s": round(len(circs) / sec, 1), "launch_ms": round(sec * 1e3, 3),
+            "gates": int(sum(len(c.gates) for c in circs)),
+            "autotuned": {"small_max_n": sm, "tile_bits": tb, "tune_s": round(tune_s, 2)},
+            "create_s": round(create_s, 2), "small_circuits": info["small_circuits"],
+            "tile_circuits": info["tile_circuits"], "graph_kernel_nodes": info["graph_nodes"],
+            "max_abs_vs_c128_sample": err}
+
+
 def main() -> None:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +203,8 @@ def main() -> None:
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-learned-eval", action="store_true")
     ap.add_argument("--eval-circuits", type=int, default=2)
+    ap.add_argument("--no-batch-eval", action="store_true")
+    ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--dump-passes", default="", help="write the last step's pass records (JSON) here")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 2^30 x 8-byte device copy (counter calibration)")
@@ -272,6 +318,8 @@ def main() -> None:
         sim.close()
         torch.cuda.empty_cache()
         out["learned_vs_plain"] = learned_vs_plain(args.eval_circuits)
+    if not args.no_batch_eval:
+        out["batch_sweep"] = batch_sweep(args.batch_reps)
     if not args.no_cpu_baseline:
         cb = cpu_baseline(circ, args.cpu_seconds)
         out["cpu_baseline"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in cb.items()

@@ -397,6 +397,7 @@ int32_t qops_batch_autotune(const qops_batch* b, const char* cache_path, int32_t
     double best = -1;
     for (int sm = 10; sm <= cap; ++sm)
         for (int tb = 11; tb <= cap; ++tb) {
+            if (tb > sm + 1) continue;     // the executor would clamp it to sm + 1
             qops_batch bb = *b;
             bb.small_max_n = sm;
             bb.tile_bits = tb;
