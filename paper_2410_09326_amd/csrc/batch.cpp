@@ -97,7 +97,8 @@ int32_t layout(qops_batch_exec* e)
     e->small_ids.clear();
     e->big_ids.clear();
     size_t out0 = 0, part0 = 0, state_off = 0;
-    int maxpass = 0, max_small_n = 1, max_L = 6;
+    int maxpass = 0, max_small_n = 1;
+    size_t max_pass_lds = 64;
     for (int i = 0; i < e->count; ++i) {
         const Plan& p = e->plans[i];
         BatchCirc& c = e->circs[i];
@@ -124,7 +125,7 @@ int32_t layout(qops_batch_exec* e)
                 h.op0 += op_base;
                 h.coef_src += (int32_t)coef_n;
                 hdrs.push_back(h);
-                max_L = std::max(max_L, h.L);
+                max_pass_lds = std::max(max_pass_lds, ((size_t)1 << h.L) * asz + (size_t)h.coef_n * csz);
             }
             maxpass = std::max(maxpass, c.npass);
             c.part0 = (int32_t)part0;
@@ -140,7 +141,8 @@ int32_t layout(qops_batch_exec* e)
     e->total_part = part0;
     e->total_state_bytes = state_off;
     e->lds_small = (int)(((size_t)1 << max_small_n) * asz);
-    e->lds_pass = (int)(((size_t)1 << max_L) * asz);
+    e->lds_pass = (int)((max_pass_lds + 15) & ~(size_t)15);
+    if (e->lds_pass > 160 * 1024) return set_error(QOPS_UNSUPPORTED, "batch pass needs more LDS than a CU has");
     e->grid = device_cus() * 2;
     // work lists: pass p of every circuit that has it; the reduction chunks
     e->pass_items.assign(maxpass, {});

@@ -353,7 +353,7 @@ __device__ void mfma_lds(typename CxT<T>::V* lds, int L, const DevOp& op, const 
     using A4 = typename CxT<T>::A4;
     constexpr int KS = 1 << (K - 1);           // k-steps of 4 real rows
     constexpr int RB = 1 << (K - 3);           // row blocks of 16 real rows
-    constexpr int RW = sizeof(T) == 4 ? (K <= 5 ? 1 : 2) : (K <= 4 ? 1 : (K == 5 ? 2 : 4));
+    constexpr int RW = sizeof(T) == 4 ? (K <= 5 ? 1 : 4) : (K <= 4 ? 1 : (K == 5 ? 2 : 4));
     constexpr int CW = 4 / RW;                 // column groups
     constexpr int RPW = RB / RW;               // row blocks per wave
     constexpr int CH = RW == 1 ? 1 : 4;        // column blocks per barrier chunk
@@ -763,7 +763,7 @@ template <typename T> constexpr int kLdsEpt = sizeof(T) == 4 ? 32 : 16;
 // of the next tile are already in flight into registers.  Tile element
 // e = 256 u + tid has physical bits 0..5 = e & 63 and bit 6+j = up_phys[j].
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1)
 tile_lds_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict__ hp, const DevOp* __restrict__ ops,
                 const T* __restrict__ coef, uint64_t ntiles)
 {
@@ -900,14 +900,21 @@ __device__ __forceinline__ void run_ops_lds(typename CxT<T>::V* lds, int n, cons
                            const T* __restrict__ coef, int tid, int nthr)
 {
     const int lane = tid & 63, wave = tid >> 6;
+    // diagonal tables (<= 64 entries) are copied to LDS first: their lookups
+    // are data dependent, and from global memory each one would wait on L2
+    __shared__ __align__(16) T ctab[2 * 64];
     for (int i = 0; i < nops; ++i) {
         const DevOp op = ops[i];
-        if (op.type == OP_DENSE_LDS)
+        if (op.type == OP_DENSE_LDS) {
             dense_lds_dispatch<T>(lds, n, op, coef + op.coef, tid, nthr);
-        else if (op.type == OP_MFMA)
+        } else if (op.type == OP_MFMA) {
             mfma_dispatch<T>(lds, n, op, coef + op.coef, lane, wave);
-        else if (op.type == OP_DIAG_LDS)
-            diag_lds<T>(lds, n, op, coef + op.coef, 0ull, tid, nthr);
+        } else if (op.type == OP_DIAG_LDS) {
+            const int cnt = 2 << op.a;
+            for (int j = tid; j < cnt; j += nthr) ctab[j] = coef[op.coef + j];
+            __syncthreads();
+            diag_lds<T>(lds, n, op, ctab, 0ull, tid, nthr);
+        }
         __syncthreads();
     }
 }
@@ -932,21 +939,15 @@ hipError_t launch_state_lds(int prec, void* state, int n, const DevOp* ops, int 
 {
     const size_t bytes = (size_t(1) << n) * (prec == 0 ? 8 : 16);
     if (prec == 0) {
-        static bool done = false;
-        if (!done) {
-            (void)hipFuncSetAttribute((const void*)state_lds_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                tile_max_lds_bytes());
-            done = true;
-        }
+        if (hipError_t e = hipFuncSetAttribute((const void*)state_lds_kernel<float>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes))
+            return e;
         hipLaunchKernelGGL(state_lds_kernel<float>, dim3(1), dim3(256), bytes, s, reinterpret_cast<float2*>(state), n,
                            ops, nops, reinterpret_cast<const float*>(coef));
     } else {
-        static bool done = false;
-        if (!done) {
-            (void)hipFuncSetAttribute((const void*)state_lds_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                tile_max_lds_bytes());
-            done = true;
-        }
+        if (hipError_t e = hipFuncSetAttribute((const void*)state_lds_kernel<double>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes))
+            return e;
         hipLaunchKernelGGL(state_lds_kernel<double>, dim3(1), dim3(256), bytes, s, reinterpret_cast<double2*>(state),
                            n, ops, nops, reinterpret_cast<const double*>(coef));
     }
@@ -1506,7 +1507,7 @@ batch_small_kernel(const int32_t* __restrict__ ids, const BatchCirc* __restrict_
 // Pass `pass` of every circuit that has one: grid-stride over its tiles.
 // Pass 0 starts from |0..0> instead of reading the state.
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1)
 batch_pass_kernel(const BatchItem* __restrict__ items, int nitems, const BatchCirc* __restrict__ circs,
                   const PassHdr* __restrict__ hdrs, const DevOp* __restrict__ ops, const T* __restrict__ coef, int pass)
 {
@@ -1522,6 +1523,10 @@ batch_pass_kernel(const BatchItem* __restrict__ items, int nitems, const BatchCi
         const int L = hp->L, nup = hp->nup;
         const uint32_t N = 1u << L;
         const uint64_t base = tile_base((uint64_t)it.tile, hp);
+        // the pass's staged coefficients (diagonal tables, matrix-core
+        // fragments) follow the tile in LDS, as in the single-circuit kernel
+        T* lcoef = reinterpret_cast<T*>(smem_raw + (size_t)N * sizeof(V));
+        for (int j = tid; j < hp->coef_n; j += 256) lcoef[j] = coef[hp->coef_src + j];
         for (uint32_t e = tid; e < N; e += 256) {
             V v;
             if (pass == 0) {
@@ -1537,7 +1542,7 @@ batch_pass_kernel(const BatchItem* __restrict__ items, int nitems, const BatchCi
         for (int j = 0; j < hp->nops; ++j) {
             const DevOp op = prog[j];
             if ((base & op.c_glob) != op.c_glob) continue;
-            const T* cf = op.b ? coef + hp->coef_src + op.coef : coef + op.coef;
+            const T* cf = op.b ? lcoef + op.coef : coef + op.coef;
             if (op.type == OP_DENSE_LDS)
                 dense_lds_dispatch<T>(lds, L, op, coef + op.coef, tid, 256);
             else if (op.type == OP_MFMA)

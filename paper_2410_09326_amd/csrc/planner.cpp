@@ -647,7 +647,9 @@ static size_t staged_bytes(const Plan& p, const LOp& o, int L)
     return 0;
 }
 
-static size_t lds_budget() { return 160 * 1024; }
+// LDS of one work-group of the LDS tile kernel: complex64 passes run two
+// work-groups per CU (the kernel is register-bounded for it), complex128 one
+static size_t lds_budget(int prec) { return prec == 0 ? 80 * 1024 : 160 * 1024; }
 
 static void emit_tile_lds(Plan& p, PassPlan& pp)
 {
@@ -671,7 +673,7 @@ static void emit_tile_lds(Plan& p, PassPlan& pp)
     // tables) contiguously, as far as they fit next to the tile in LDS
     const size_t sz = p.prec == 0 ? 4 : 8;
     const size_t tile_bytes = (size_t(1) << pp.L) * 2 * sz;
-    size_t room = lds_budget() > tile_bytes ? (lds_budget() - tile_bytes) / sz : 0;
+    size_t room = lds_budget(p.prec) > tile_bytes ? (lds_budget(p.prec) - tile_bytes) / sz : 0;
     h.coef_src = (int)p.coef.size();
     int staged = 0;
     for (int i = h.op0; i < h.op0 + h.nops; ++i) {
@@ -737,7 +739,7 @@ static void emit_sweep(Plan& p, PassPlan& pp)
 // ---------------------------------------------------------------------------
 
 static size_t staged_bytes(const Plan& p, const LOp& o, int L);
-static size_t lds_budget();
+static size_t lds_budget(int prec);
 
 static void pick_reg_variant(int n, int prec, int want_up, int& R, int& W)
 {
@@ -879,7 +881,10 @@ static void pack(Plan& p)
         // an LDS pass also keeps its matrix-core fragments next to the tile
         const size_t sb = staged_bytes(p, o, 6 + cap_lds);
         const size_t tile_bytes = (size_t(1) << (6 + cap_lds)) * (p.prec == 0 ? 8 : 16);
-        const bool lds_full = d2 && staged + sb + tile_bytes > lds_budget() && sb > 0 && staged > 0;
+        // complex128 passes keep all their fragments in LDS (one work-group per
+        // CU); complex64 passes read what does not fit from L2 instead
+        const bool lds_full = p.prec == 1 && d2 && staged + sb + tile_bytes > lds_budget(p.prec) && sb > 0 &&
+                              staged > 0;
         if (__builtin_popcountll(S | need) > cap || lds_full) {
             flush();
             cur.lop.push_back((int)i);
