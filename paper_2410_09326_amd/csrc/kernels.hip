@@ -98,6 +98,19 @@ __device__ __forceinline__ uint32_t spread_mask(uint32_t g, uint32_t mask)
     return g;
 }
 
+// Bits of g, lowest first, placed at the set positions of dmask (lowest first).
+__device__ __forceinline__ uint32_t deposit_bits(uint32_t g, uint32_t dmask)
+{
+    uint32_t r = 0;
+    while (dmask) {
+        const uint32_t low = dmask & (0u - dmask);
+        if (g & 1u) r |= low;
+        g >>= 1;
+        dmask &= dmask - 1u;
+    }
+    return r;
+}
+
 __device__ __forceinline__ uint64_t spread_mask64(uint64_t g, uint64_t mask)
 {
     while (mask) {
@@ -360,12 +373,13 @@ __device__ void mfma_lds(typename CxT<T>::V* lds, int L, const DevOp& op, const 
     const int rg = wave % RW, cg = wave / RW;
     const int ncb = 1 << (L - K - 4);
     const int nper = (ncb + CW - 1) / CW;      // same for every wave
-    uint32_t mask = 0, bit[K];
+    uint32_t bit[K];
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        bit[j] = 1u << op.pos[j];
-        mask |= bit[j];
-    }
+    for (int j = 0; j < K; ++j) bit[j] = 1u << op.pos[j];
+    // the 16 columns of a column block differ in the four tile positions of
+    // op.c_lane (chosen on the host so that their LDS banks differ); the
+    // block number fills the other free positions, op.c_wave
+    const uint32_t gl = deposit_bits((uint32_t)(lane & 15), op.c_lane);
     auto toff = [&](uint32_t s) {              // s is a compile-time constant at every call
         uint32_t o = 0;
 #pragma unroll
@@ -383,18 +397,24 @@ __device__ void mfma_lds(typename CxT<T>::V* lds, int L, const DevOp& op, const 
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) av[r][ks] = A[((rg * RPW + r) * KS + ks) * 64 + lane];
     const T* __restrict__ ldsf = reinterpret_cast<const T*>(lds);
+    // the wave's column blocks are cg, cg + CW, ...; their free-position bits
+    // advance by a masked add (carries pass through the positions outside
+    // the mask), one scalar step per block
+    const uint32_t wmask = op.c_wave;
+    const uint32_t wstep = deposit_bits((uint32_t)CW, wmask);
+    uint32_t gblk = deposit_bits((uint32_t)cg, wmask);
     for (int i0 = 0; i0 < nper; i0 += CH) {
         A4 acc[RPW][CH];
-        uint32_t gsw[CH];
+        uint32_t gsw[CH], gcol[CH];
         sfor<CH>([&](auto cc) {
             constexpr int c = decltype(cc)::value;
             const int blk = cg + (i0 + c) * CW;
 #pragma unroll
             for (int r = 0; r < RPW; ++r) acc[r][c] = A4{0, 0, 0, 0};
-            gsw[c] = 0;
+            gcol[c] = gl | gblk;
+            gsw[c] = swz(gcol[c]);
+            gblk = ((gblk | ~wmask) + wstep) & wmask;
             if (i0 + c < nper && blk < ncb) {
-                const uint32_t col = (uint32_t)blk * 16 + (lane & 15);
-                gsw[c] = swz(spread_mask(col, mask));
                 const uint32_t g_in = gsw[c] ^ in_sw;
 #pragma unroll
                 for (int ks = 0; ks < KS; ++ks) {
@@ -414,8 +434,7 @@ __device__ void mfma_lds(typename CxT<T>::V* lds, int L, const DevOp& op, const 
             constexpr int c = decltype(cc)::value;
             const int blk = cg + (i0 + c) * CW;
             if (i0 + c < nper && blk < ncb) {
-                const uint32_t col = (uint32_t)blk * 16 + (lane & 15);
-                if ((spread_mask(col, mask) & op.c_tile) == op.c_tile) {
+                if ((gcol[c] & op.c_tile) == op.c_tile) {
                     const uint32_t g_out = gsw[c] ^ out_sw;
 #pragma unroll
                     for (int r = 0; r < RPW; ++r) {

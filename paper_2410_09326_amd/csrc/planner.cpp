@@ -444,6 +444,41 @@ static bool lds_capable(const Plan& p, const LOp& o, int L)
 
 // LDS-resident ops (tile LDS, whole-state LDS and sweep share the encoding;
 // `tpos(phys)` maps a physical bit to a tile position or -1 if outside).
+// Column positions of a matrix-core op: a column is one group of 2^k
+// amplitudes (one value of the L-k free tile positions); the 16 columns a
+// wave reads at once differ in four free positions (c_lane), the column
+// block number fills the rest (c_wave).  The LDS swizzle folds tile
+// positions 5..8 onto 0..3, and the 16 lanes of a read hit distinct bank
+// pairs when the four positions fall on distinct residues of that fold, so
+// those are taken first.
+static void set_mfma_columns(DevOp& d, int k, int L)
+{
+    uint32_t opm = 0;
+    for (int j = 0; j < k; ++j) opm |= 1u << d.pos[j];
+    int pick[4] = {-1, -1, -1, -1};
+    uint32_t used = 0;
+    auto bank_class = [](int tp) { return tp < 4 ? tp : (tp >= 5 && tp <= 8 ? tp - 5 : -1); };
+    for (int tp = 0; tp < L; ++tp) {
+        if (opm & (1u << tp)) continue;
+        const int r = bank_class(tp);
+        if (r >= 0 && pick[r] < 0) {
+            pick[r] = tp;
+            used |= 1u << tp;
+        }
+    }
+    for (int i = 0; i < 4; ++i)
+        if (pick[i] < 0)
+            for (int tp = 0; tp < L; ++tp)
+                if (!(opm & (1u << tp)) && !(used & (1u << tp))) {
+                    pick[i] = tp;
+                    used |= 1u << tp;
+                    break;
+                }
+    const uint32_t all = (L >= 32 ? ~0u : ((1u << L) - 1u));
+    d.c_lane = used;
+    d.c_wave = all & ~opm & ~used;
+}
+
 template <typename F>
 static void emit_lds_op(Plan& p, const LOp& o, int L, F tpos, PassPlan& pp)
 {
@@ -483,6 +518,7 @@ static void emit_lds_op(Plan& p, const LOp& o, int L, F tpos, PassPlan& pp)
             d.type = OP_MFMA;
             d.coef = push_mfma_coef(p, m, k);
             pp.n_mfma++;
+            set_mfma_columns(d, k, L);
         } else {
             d.type = OP_DENSE_LDS;
             d.coef = push_coef(p, m);
