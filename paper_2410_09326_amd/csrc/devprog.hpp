@@ -64,7 +64,8 @@ struct PassHdr {
     int32_t run_start[QOPS_MAX_RUNS];  // physical start bit of each run
     int32_t run_len[QOPS_MAX_RUNS];
     int32_t run_gshift[QOPS_MAX_RUNS]; // bit offset of the run inside the tile number
-    int32_t pad[1];
+    int32_t hoist;                  // LDS tile pass: op (relative to op0) whose matrix-core
+                                    //   fragments stay in registers, or -1
 };
 
 // Batched executor records.

@@ -359,17 +359,41 @@ __device__ void diag_lds(typename CxT<T>::V* lds, int L, const DevOp& op, const 
 // row 4 ks + l/16 of column l%16.  LDS slots are swizzled (swz), whose
 // linearity turns every address into one XOR of a per-lane and a uniform part.
 template <int K, typename T>
-__device__ void mfma_lds(typename CxT<T>::V* lds, int L, const DevOp& op, const T* __restrict__ A, int lane,
-                         int wave)
+struct MfmaShape {
+    static constexpr int KS = 1 << (K - 1);    // k-steps of 4 real rows
+    static constexpr int RB = 1 << (K - 3);    // row blocks of 16 real rows
+    static constexpr int RW = sizeof(T) == 4 ? (K <= 5 ? 1 : 4) : (K <= 4 ? 1 : (K == 5 ? 2 : 4));
+    static constexpr int CW = 4 / RW;          // column groups
+    static constexpr int RPW = RB / RW;        // row blocks per wave
+    // column blocks in flight (one barrier per chunk if RW > 1): eight
+    // independent accumulator chains per wave
+    static constexpr int CH = RPW >= 4 ? 2 : 4;
+};
+
+// The A fragments of a wave's row blocks (registers).
+template <int K, typename T>
+using MfmaFrag = T[MfmaShape<K, T>::RPW][MfmaShape<K, T>::KS];
+
+// The A fragments of the wave's row blocks, from global memory or LDS.
+template <int K, typename T>
+__device__ __forceinline__ void mfma_load_a(MfmaFrag<K, T>& av, const T* __restrict__ A, int lane, int wave)
+{
+    using S = MfmaShape<K, T>;
+    const int rg = wave % S::RW;
+#pragma unroll
+    for (int r = 0; r < S::RPW; ++r)
+#pragma unroll
+        for (int ks = 0; ks < S::KS; ++ks) av[r][ks] = A[((rg * S::RPW + r) * S::KS + ks) * 64 + lane];
+}
+
+template <int K, typename T>
+__device__ __forceinline__ void mfma_core(typename CxT<T>::V* lds, int L, const DevOp& op, const MfmaFrag<K, T>& av,
+                                          int lane, int wave)
 {
     using V = typename CxT<T>::V;
     using A4 = typename CxT<T>::A4;
-    constexpr int KS = 1 << (K - 1);           // k-steps of 4 real rows
-    constexpr int RB = 1 << (K - 3);           // row blocks of 16 real rows
-    constexpr int RW = sizeof(T) == 4 ? (K <= 5 ? 1 : 4) : (K <= 4 ? 1 : (K == 5 ? 2 : 4));
-    constexpr int CW = 4 / RW;                 // column groups
-    constexpr int RPW = RB / RW;               // row blocks per wave
-    constexpr int CH = RW == 1 ? 1 : 4;        // column blocks per barrier chunk
+    using S = MfmaShape<K, T>;
+    constexpr int KS = S::KS, RW = S::RW, CW = S::CW, RPW = S::RPW, CH = S::CH;
     const int rg = wave % RW, cg = wave / RW;
     const int ncb = 1 << (L - K - 4);
     const int nper = (ncb + CW - 1) / CW;      // same for every wave
@@ -391,11 +415,6 @@ __device__ void mfma_lds(typename CxT<T>::V* lds, int L, const DevOp& op, const 
     const uint32_t in_sw = swz((krow >> 1) ? bit[0] : 0u);                           // bit 0 of s
     const uint32_t out_sw = swz(((krow & 1) ? bit[1] : 0u) | ((krow >> 1) ? bit[2] : 0u));
     const uint32_t part = (uint32_t)(krow & 1);                                       // re / im
-    T av[RPW][KS];
-#pragma unroll
-    for (int r = 0; r < RPW; ++r)
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) av[r][ks] = A[((rg * RPW + r) * KS + ks) * 64 + lane];
     const T* __restrict__ ldsf = reinterpret_cast<const T*>(lds);
     // the wave's column blocks are cg, cg + CW, ...; their free-position bits
     // advance by a masked add (carries pass through the positions outside
@@ -403,66 +422,97 @@ __device__ void mfma_lds(typename CxT<T>::V* lds, int L, const DevOp& op, const 
     const uint32_t wmask = op.c_wave;
     const uint32_t wstep = deposit_bits((uint32_t)CW, wmask);
     uint32_t gblk = deposit_bits((uint32_t)cg, wmask);
+    auto mfma = [](const T a, const T b, const A4 c) -> A4 {
+        if constexpr (sizeof(T) == 4) return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+        else return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    };
     for (int i0 = 0; i0 < nper; i0 += CH) {
         A4 acc[RPW][CH];
-        uint32_t gsw[CH], gcol[CH];
+        uint32_t gsw[CH], gcol[CH], gin[CH];
+        bool ok[CH];
+        // CH column blocks at once; a block past the wave's last one reads an
+        // in-range column (the masked increment wraps inside the mask) and is
+        // not written back, so the loads and MFMAs below need no branches
         sfor<CH>([&](auto cc) {
             constexpr int c = decltype(cc)::value;
             const int blk = cg + (i0 + c) * CW;
+            ok[c] = i0 + c < nper && blk < ncb;
 #pragma unroll
             for (int r = 0; r < RPW; ++r) acc[r][c] = A4{0, 0, 0, 0};
             gcol[c] = gl | gblk;
             gsw[c] = swz(gcol[c]);
+            gin[c] = gsw[c] ^ in_sw;
             gblk = ((gblk | ~wmask) + wstep) & wmask;
-            if (i0 + c < nper && blk < ncb) {
-                const uint32_t g_in = gsw[c] ^ in_sw;
-#pragma unroll
-                for (int ks = 0; ks < KS; ++ks) {
-                    const T b = ldsf[2 * (g_in ^ swz(toff((uint32_t)(2 * ks)))) + part];
-#pragma unroll
-                    for (int r = 0; r < RPW; ++r) {
-                        if constexpr (sizeof(T) == 4)
-                            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[r][ks], b, acc[r][c], 0, 0, 0);
-                        else
-                            acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r][ks], b, acc[r][c], 0, 0, 0);
-                    }
-                }
+        });
+        // B values one k-step ahead of the MFMAs that use them
+        T bq[2][CH];
+        sfor<CH>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            bq[0][c] = ldsf[2 * (gin[c] ^ swz(toff(0u))) + part];
+        });
+        sfor<KS>([&](auto kc) {
+            constexpr int ks = decltype(kc)::value;
+            constexpr int cur = ks & 1;
+            if constexpr (ks + 1 < KS) {
+                const uint32_t nx = swz(toff((uint32_t)(2 * (ks + 1))));
+                sfor<CH>([&](auto cc) {
+                    constexpr int c = decltype(cc)::value;
+                    bq[cur ^ 1][c] = ldsf[2 * (gin[c] ^ nx) + part];
+                });
             }
+            // keep the next step's loads ahead of this step's MFMAs (the
+            // scheduler would otherwise sink each load next to its use)
+            __builtin_amdgcn_sched_barrier(0);
+            sfor<CH>([&](auto cc) {
+                constexpr int c = decltype(cc)::value;
+#pragma unroll
+                for (int r = 0; r < RPW; ++r) acc[r][c] = mfma(av[r][ks], bq[cur][c], acc[r][c]);
+            });
+            __builtin_amdgcn_sched_barrier(0);
         });
         if constexpr (RW > 1) __syncthreads();   // the chunk's B fragments are read
         sfor<CH>([&](auto cc) {
             constexpr int c = decltype(cc)::value;
-            const int blk = cg + (i0 + c) * CW;
-            if (i0 + c < nper && blk < ncb) {
-                if ((gcol[c] & op.c_tile) == op.c_tile) {
-                    const uint32_t g_out = gsw[c] ^ out_sw;
+            if (ok[c] && (gcol[c] & op.c_tile) == op.c_tile) {
+                const uint32_t g_out = gsw[c] ^ out_sw;
 #pragma unroll
-                    for (int r = 0; r < RPW; ++r) {
-                        const int rb = rg * RPW + r;
-                        const uint32_t o0 = g_out ^ swz(toff((uint32_t)(8 * rb)));
-                        V w0, w1;
-                        w0.x = acc[r][c][0];
-                        w0.y = acc[r][c][1];
-                        w1.x = acc[r][c][2];
-                        w1.y = acc[r][c][3];
-                        lds[o0] = w0;
-                        lds[o0 ^ swz(bit[0])] = w1;
-                    }
+                for (int r = 0; r < RPW; ++r) {
+                    const int rb = rg * RPW + r;
+                    const uint32_t o0 = g_out ^ swz(toff((uint32_t)(8 * rb)));
+                    V w0, w1;
+                    w0.x = acc[r][c][0];
+                    w0.y = acc[r][c][1];
+                    w1.x = acc[r][c][2];
+                    w1.y = acc[r][c][3];
+                    lds[o0] = w0;
+                    lds[o0 ^ swz(bit[0])] = w1;
                 }
             }
         });
     }
 }
 
-template <typename T>
+template <int K, typename T>
+__device__ void mfma_lds(typename CxT<T>::V* lds, int L, const DevOp& op, const T* __restrict__ A, int lane,
+                         int wave)
+{
+    MfmaFrag<K, T> av;
+    mfma_load_a<K, T>(av, A, lane, wave);
+    mfma_core<K, T>(lds, L, op, av, lane, wave);
+}
+
+// Matrix-core blocks of at most KMAX qubits (a kernel that keeps a larger
+// block's fragments resident dispatches only the small ones here).
+template <typename T, int KMAX = 6>
 __device__ void mfma_dispatch(typename CxT<T>::V* lds, int L, const DevOp& op, const T* __restrict__ A, int lane,
                               int wave)
 {
+    if (op.a > KMAX) return;
     switch (op.a) {
     case 3: mfma_lds<3, T>(lds, L, op, A, lane, wave); break;
     case 4: mfma_lds<4, T>(lds, L, op, A, lane, wave); break;
-    case 5: mfma_lds<5, T>(lds, L, op, A, lane, wave); break;
-    case 6: mfma_lds<6, T>(lds, L, op, A, lane, wave); break;
+    case 5: if constexpr (KMAX >= 5) mfma_lds<5, T>(lds, L, op, A, lane, wave); break;
+    case 6: if constexpr (KMAX >= 6) mfma_lds<6, T>(lds, L, op, A, lane, wave); break;
     default: break;
     }
 }
@@ -781,7 +831,10 @@ template <typename T> constexpr int kLdsEpt = sizeof(T) == 4 ? 32 : 16;
 // over tiles; while the operations of tile t run on its LDS copy, the loads
 // of the next tile are already in flight into registers.  Tile element
 // e = 256 u + tid has physical bits 0..5 = e & 63 and bit 6+j = up_phys[j].
-template <typename T>
+// HK > 0: the pass's one HK-qubit matrix-core block (op hp->hoist) keeps its
+// A fragments in registers for every tile of the work-group, and the other
+// matrix-core blocks of the pass have at most 4 qubits.
+template <typename T, int HK>
 __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1)
 tile_lds_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict__ hp, const DevOp* __restrict__ ops,
                 const T* __restrict__ coef, uint64_t ntiles)
@@ -801,6 +854,14 @@ tile_lds_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict__
     {
         const T* __restrict__ src = coef + hp->coef_src;
         for (int i = tid; i < hp->coef_n; i += 256) lcoef[i] = src[i];
+    }
+    constexpr int HKK = HK > 0 ? HK : 3;
+    MfmaFrag<HKK, T> hav;
+    const int hoist = HK > 0 ? hp->hoist : -1;
+    if constexpr (HK > 0) {
+        __syncthreads();   // staged coefficients visible
+        const DevOp hop = prog[hoist];
+        mfma_load_a<HKK, T>(hav, hop.b ? lcoef + hop.coef : coef + hop.coef, lane, wave);
     }
     const uint64_t dep_thr = dep_up((uint32_t)(tid >> 6), hp->up_phys, nup);
     // element 256 u + tid: bit b of u selects physical bit up_phys[2 + b]
@@ -846,12 +907,18 @@ tile_lds_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict__
             const DevOp op = prog[i];
             if ((base & op.c_glob) != op.c_glob) continue;
             const T* cf = op.b ? lcoef + op.coef : coef + op.coef;
-            if (op.type == OP_DENSE_LDS)
+            if (op.type == OP_DENSE_LDS) {
                 dense_lds_dispatch<T>(lds, L, op, coef + op.coef, tid, 256);
-            else if (op.type == OP_MFMA)
-                mfma_dispatch<T>(lds, L, op, cf, lane, wave);
-            else if (op.type == OP_DIAG_LDS)
+            } else if (op.type == OP_MFMA) {
+                if constexpr (HK > 0) {
+                    if (i == hoist) mfma_core<HKK, T>(lds, L, op, hav, lane, wave);
+                    else mfma_dispatch<T, 4>(lds, L, op, cf, lane, wave);
+                } else {
+                    mfma_dispatch<T>(lds, L, op, cf, lane, wave);
+                }
+            } else if (op.type == OP_DIAG_LDS) {
                 diag_lds<T>(lds, L, op, cf, base, tid, 256);
+            }
             __syncthreads();
         }
         {
@@ -879,8 +946,24 @@ static int num_cus()
     return g_num_cus;
 }
 
+template <typename T, int HK>
+static hipError_t launch_tile_lds_t(void* state, const PassHdr* hdr, const DevOp* ops, const void* coef,
+                                    uint64_t grid, uint64_t ntiles, int lds_bytes, hipStream_t s)
+{
+    using V = typename CxT<T>::V;
+    static bool done = false;
+    if (!done) {
+        (void)hipFuncSetAttribute((const void*)tile_lds_kernel<T, HK>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  tile_max_lds_bytes());
+        done = true;
+    }
+    hipLaunchKernelGGL((tile_lds_kernel<T, HK>), dim3((unsigned)grid), dim3(256), lds_bytes, s,
+                       reinterpret_cast<V*>(state), hdr, ops, reinterpret_cast<const T*>(coef), ntiles);
+    return hipGetLastError();
+}
+
 hipError_t launch_tile_lds(int prec, void* state, const PassHdr* hdr, const DevOp* ops, const void* coef,
-                           uint64_t ntiles, int L, int lds_bytes, int grid_cap, hipStream_t s)
+                           uint64_t ntiles, int L, int lds_bytes, int grid_cap, int hoist_k, hipStream_t s)
 {
     (void)L;
     // persistent grid: as many work-groups as fit on the chip at this LDS size
@@ -889,25 +972,11 @@ hipError_t launch_tile_lds(int prec, void* state, const PassHdr* hdr, const DevO
     if (grid_cap > 0 && grid > (uint64_t)grid_cap) grid = (uint64_t)grid_cap;
     if (grid == 0) grid = 1;
     if (prec == 0) {
-        static bool done = false;
-        if (!done) {
-            (void)hipFuncSetAttribute((const void*)tile_lds_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      tile_max_lds_bytes());
-            done = true;
-        }
-        hipLaunchKernelGGL(tile_lds_kernel<float>, dim3((unsigned)grid), dim3(256), lds_bytes, s,
-                           reinterpret_cast<float2*>(state), hdr, ops, reinterpret_cast<const float*>(coef), ntiles);
-    } else {
-        static bool done = false;
-        if (!done) {
-            (void)hipFuncSetAttribute((const void*)tile_lds_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      tile_max_lds_bytes());
-            done = true;
-        }
-        hipLaunchKernelGGL(tile_lds_kernel<double>, dim3((unsigned)grid), dim3(256), lds_bytes, s,
-                           reinterpret_cast<double2*>(state), hdr, ops, reinterpret_cast<const double*>(coef), ntiles);
+        if (hoist_k == 6) return launch_tile_lds_t<float, 6>(state, hdr, ops, coef, grid, ntiles, lds_bytes, s);
+        if (hoist_k == 5) return launch_tile_lds_t<float, 5>(state, hdr, ops, coef, grid, ntiles, lds_bytes, s);
+        return launch_tile_lds_t<float, 0>(state, hdr, ops, coef, grid, ntiles, lds_bytes, s);
     }
-    return hipGetLastError();
+    return launch_tile_lds_t<double, 0>(state, hdr, ops, coef, grid, ntiles, lds_bytes, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -20,8 +20,9 @@ hipError_t launch_tile_pass(int prec, int R, int W, void* state, const PassHdr* 
                             const void* coef, uint64_t ntiles, int lds_bytes, int grid_cap, hipStream_t s);
 
 // LDS tile pass (dense blocks): tile of 2^L amplitudes in LDS, 256 threads.
+// hoist_k: qubits of the block whose fragments stay in registers (hdr->hoist), 0 if none.
 hipError_t launch_tile_lds(int prec, void* state, const PassHdr* hdr, const DevOp* ops, const void* coef,
-                           uint64_t ntiles, int L, int lds_bytes, int grid_cap, hipStream_t s);
+                           uint64_t ntiles, int L, int lds_bytes, int grid_cap, int hoist_k, hipStream_t s);
 
 // Whole state in one work-group's LDS (n <= 13 for c64, <= 12 for c128).
 hipError_t launch_state_lds(int prec, void* state, int n, const DevOp* ops, int nops, const void* coef,

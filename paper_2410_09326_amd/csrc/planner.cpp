@@ -570,6 +570,7 @@ static void emit_tile_reg(Plan& p, PassPlan& pp)
     uint32_t map = mapword(regs);
     PassHdr h;
     std::memset(&h, 0, sizeof(h));
+    h.hoist = -1;
     h.n = p.n;
     h.L = pp.L;
     h.nup = U;
@@ -729,6 +730,18 @@ static void emit_tile_lds(Plan& p, PassPlan& pp)
     }
     h.coef_n = staged;
     h.lds_bytes = (int)(tile_bytes + (size_t)staged * sz);
+    // complex64: a pass with exactly one matrix-core block of 5 or 6 qubits
+    // keeps that block's fragments in registers across its tiles
+    h.hoist = -1;
+    if (p.prec == 0) {
+        int big = 0, at = -1;
+        for (int i = h.op0; i < h.op0 + h.nops; ++i)
+            if (p.dops[i].type == OP_MFMA && p.dops[i].a >= 5) {
+                ++big;
+                at = i - h.op0;
+            }
+        if (big == 1) h.hoist = at;
+    }
     pp.op0 = h.op0;
     pp.nops = h.nops;
     pp.hdr = (int)p.hdrs.size();

@@ -89,8 +89,10 @@ int32_t launch_pass(qops_sim* h, const Plan& p, const PassPlan& pp)
     }
     case PASS_TILE_LDS: {
         const uint64_t ntiles = 1ull << (p.n - pp.L);
-        e = launch_tile_lds(p.prec, h->state, dh + pp.hdr, dops, p.d_coef, ntiles, pp.L, p.hdrs[pp.hdr].lds_bytes,
-                            h->grid_cap, h->stream);
+        const PassHdr& hh = p.hdrs[pp.hdr];
+        const int hoist_k = hh.hoist >= 0 ? p.dops[hh.op0 + hh.hoist].a : 0;
+        e = launch_tile_lds(p.prec, h->state, dh + pp.hdr, dops, p.d_coef, ntiles, pp.L, hh.lds_bytes, h->grid_cap,
+                            hoist_k, h->stream);
         break;
     }
     case PASS_STATE_LDS:
