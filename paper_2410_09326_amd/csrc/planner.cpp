@@ -908,43 +908,79 @@ static void pack(Plan& p)
         dense = false;
         staged = 0;
     };
-    for (size_t i = 0; i < p.lops.size(); ++i) {
-        const LOp& o = p.lops[i];
-        if (o.kind == LOp::PSWAP) {
-            flush();
-            PassPlan sp;
-            sp.type = PASS_SWAP_BITS;
-            sp.swap_a = o.t[0];
-            sp.swap_b = o.t[1];
-            sp.bytes_alg = state_bytes;
-            sp.lop.push_back((int)i);
-            p.passes.push_back(sp);
-            continue;
-        }
+    // Greedy packing with look-ahead: a pass opens with the first op not yet
+    // placed and then scans forward, taking every op whose bits fit the tile
+    // and which commutes with each op skipped so far (so it may move ahead of
+    // them).  Two ops commute when neither's non-diagonal target bits meet
+    // any bit of the other (shared bits are then controls or diagonal bits of
+    // both).  A physical swap ends the scan.
+    const size_t nl = p.lops.size();
+    const size_t window = 256;
+    std::vector<char> placed(nl, 0);
+    auto need_of = [](const LOp& o) {
         uint64_t need = 0;
         if (o.kind != LOp::DIAG)
             for (int j = 0; j < o.k; ++j)
                 if (o.t[j] >= 6) need |= 1ull << o.t[j];
+        return need;
+    };
+    // the op joins the current pass if its bits fit (and, for complex128, its
+    // staged fragments fit next to the tile)
+    auto try_add = [&](size_t i) -> bool {
+        const LOp& o = p.lops[i];
+        const uint64_t need = need_of(o);
         const bool d2 = dense || o.kind == LOp::DENSE || p.par.force_lds;
         const int cap = d2 ? cap_lds : cap_reg;
-        // an LDS pass also keeps its matrix-core fragments next to the tile
         const size_t sb = staged_bytes(p, o, 6 + cap_lds);
         const size_t tile_bytes = (size_t(1) << (6 + cap_lds)) * (p.prec == 0 ? 8 : 16);
         // complex128 passes keep all their fragments in LDS (one work-group per
         // CU); complex64 passes read what does not fit from L2 instead
         const bool lds_full = p.prec == 1 && d2 && staged + sb + tile_bytes > lds_budget(p.prec) && sb > 0 &&
                               staged > 0;
-        if (__builtin_popcountll(S | need) > cap || lds_full) {
+        if (!cur.lop.empty() && (__builtin_popcountll(S | need) > cap || lds_full)) return false;
+        cur.lop.push_back((int)i);
+        S |= need;
+        dense = d2;
+        staged += sb;
+        return true;
+    };
+    size_t first = 0;
+    while (first < nl) {
+        if (placed[first]) {
+            ++first;
+            continue;
+        }
+        const LOp& o0 = p.lops[first];
+        if (o0.kind == LOp::PSWAP) {
             flush();
-            cur.lop.push_back((int)i);
-            S = need;
-            dense = o.kind == LOp::DENSE || p.par.force_lds;
-            staged = sb;
-        } else {
-            cur.lop.push_back((int)i);
-            S |= need;
-            dense = d2;
-            staged += sb;
+            PassPlan sp;
+            sp.type = PASS_SWAP_BITS;
+            sp.swap_a = o0.t[0];
+            sp.swap_b = o0.t[1];
+            sp.bytes_alg = state_bytes;
+            sp.lop.push_back((int)first);
+            p.passes.push_back(sp);
+            placed[first] = 1;
+            continue;
+        }
+        flush();
+        try_add(first);
+        placed[first] = 1;
+        uint64_t skip_touch = 0, skip_nd = 0;
+        const size_t stop = std::min(nl, first + 1 + window);
+        for (size_t j = first + 1; j < stop; ++j) {
+            if (placed[j]) continue;
+            const LOp& o = p.lops[j];
+            if (o.kind == LOp::PSWAP) break;
+            const uint64_t tj = o.touch(), nj = o.tmask();
+            const bool commutes = (nj & skip_touch) == 0 && (tj & skip_nd) == 0;
+            if (commutes && try_add(j)) {
+                placed[j] = 1;
+            } else {
+                skip_touch |= tj;
+                skip_nd |= nj;
+                if (__builtin_popcountll(skip_nd) >= n) break;   // nothing can pass any more
+            }
         }
     }
     flush();
