@@ -313,8 +313,9 @@ int32_t qops_profile_create(int32_t n, qops_profile** out);
 /* Many small, uneven circuits (a parameter sweep, paper Sec. IV-E: the same
  * ansatz simulated again and again with new angles) run as ONE graph launch:
  * circuits of up to small_max_n qubits each run start to finish in one
- * work-group's LDS; the larger ones are planned into tile passes and graph
- * node p runs pass p of every circuit that has one.  Every circuit starts in
+ * work-group's LDS; the larger ones are planned into tile passes (register
+ * or LDS tiles) and the graph nodes of step p run pass p of every circuit
+ * that has one, one node per kernel kind.  Every circuit starts in
  * |0..0>; the outputs are <Z_q> of every logical qubit of every circuit
  * (FP64, deterministic), concatenated in circuit order (sum of n_i doubles).
  * SWAP gates are handled virtually. */

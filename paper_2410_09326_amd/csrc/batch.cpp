@@ -1,9 +1,10 @@
 // Batched executor: many small, uneven circuits (parameter sweeps, paper
 // Sec. IV-E) in one graph launch.  Circuits whose whole state fits in one
 // work-group's LDS run start to finish in one kernel (one work-group each);
-// the larger ones are planned into LDS tile passes and node p of the graph
-// runs pass p of every circuit that has one.  <Z_i> of every circuit is
-// reduced on the device in FP64 and read back once.
+// the larger ones are planned into tile passes (register tiles, or LDS tiles
+// where a pass holds dense blocks) and pass p of every circuit that has one
+// runs in the graph nodes of step p, one node per kernel kind.  <Z_i> of
+// every circuit is reduced on the device in FP64 and read back once.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,12 +28,20 @@ struct qops_batch_exec {
     std::vector<qops::Plan> plans;
     std::vector<BatchCirc> circs;
     std::vector<int32_t> small_ids, big_ids;
-    std::vector<std::vector<BatchItem>> pass_items;
+    struct Node {                       // one kernel of step `pass`
+        int pass = 0;
+        int kind = 0;                   // 0: register tiles (R, W), 1: LDS tiles
+        int R = 0, W = 0;
+        int lds = 0;                    // dynamic LDS bytes
+        std::vector<BatchItem> items;
+        BatchItem* d = nullptr;
+    };
+    std::vector<Node> nodes;
     std::vector<BatchItem> z_items;
     std::vector<size_t> coef_base;      // offset of each plan's coefficients in the batch image
     std::vector<size_t> state_base;     // byte offset of each tile-pass circuit's state
     size_t total_out = 0, total_part = 0, total_state_bytes = 0;
-    int lds_small = 0, lds_pass = 0, grid = 0;
+    int lds_small = 0, grid = 0;
     // device
     BatchCirc* d_circs = nullptr;
     PassHdr* d_hdrs = nullptr;
@@ -40,7 +49,6 @@ struct qops_batch_exec {
     void* d_coef = nullptr;
     int32_t* d_small = nullptr;
     int32_t* d_big = nullptr;
-    std::vector<BatchItem*> d_items;
     BatchItem* d_zitems = nullptr;
     double* d_part = nullptr;
     double* d_out = nullptr;
@@ -61,14 +69,16 @@ int32_t plan_all(qops_batch_exec* e, const qops_batch* b)
         const int n = b->n[i];
         if (n < 1 || n > 26) return set_error(QOPS_UNSUPPORTED, "batch circuits need 1 <= n <= 26");
         PlanParams par = params_from(nullptr, n, b->precision);
-        par.force_lds = 1;
         par.state_lds_max_n = e->small_max_n;
         par.L_lds = std::min(e->tile_bits, n);
+        // register tiles of the same width: R register bits, the rest wave bits
+        par.W = std::max(0, std::min(2, std::min(e->tile_bits, n) - 6 - par.R));
         Err er = build_plan(n, b->precision, nullptr, b->gates[i], b->n_gates[i], par, e->plans[i]);
         if (!er.ok()) return set_error(er.code, "circuit " + std::to_string(i) + ": " + er.msg);
         const Plan& p = e->plans[i];
         for (const PassPlan& pp : p.passes) {
-            const bool ok = n <= e->small_max_n ? pp.type == PASS_STATE_LDS : pp.type == PASS_TILE_LDS;
+            const bool ok = n <= e->small_max_n ? pp.type == PASS_STATE_LDS
+                                                : (pp.type == PASS_TILE_LDS || pp.type == PASS_TILE_REG);
             if (!ok)
                 return set_error(QOPS_UNSUPPORTED, "circuit " + std::to_string(i) +
                                                        ": needs an operation the batched executor does not run "
@@ -98,7 +108,6 @@ int32_t layout(qops_batch_exec* e)
     e->big_ids.clear();
     size_t out0 = 0, part0 = 0, state_off = 0;
     int maxpass = 0, max_small_n = 1;
-    size_t max_pass_lds = 64;
     for (int i = 0; i < e->count; ++i) {
         const Plan& p = e->plans[i];
         BatchCirc& c = e->circs[i];
@@ -125,7 +134,6 @@ int32_t layout(qops_batch_exec* e)
                 h.op0 += op_base;
                 h.coef_src += (int32_t)coef_n;
                 hdrs.push_back(h);
-                max_pass_lds = std::max(max_pass_lds, ((size_t)1 << h.L) * asz + (size_t)h.coef_n * csz);
             }
             maxpass = std::max(maxpass, c.npass);
             c.part0 = (int32_t)part0;
@@ -141,20 +149,45 @@ int32_t layout(qops_batch_exec* e)
     e->total_part = part0;
     e->total_state_bytes = state_off;
     e->lds_small = (int)(((size_t)1 << max_small_n) * asz);
-    e->lds_pass = (int)((max_pass_lds + 15) & ~(size_t)15);
-    if (e->lds_pass > 160 * 1024) return set_error(QOPS_UNSUPPORTED, "batch pass needs more LDS than a CU has");
     e->grid = device_cus() * 2;
-    // work lists: pass p of every circuit that has it; the reduction chunks
-    e->pass_items.assign(maxpass, {});
+    // work lists: pass p of every circuit that has it, one list per kernel
+    // kind (register tiles of each R/W split, LDS tiles); the reduction chunks
+    e->nodes.clear();
     e->z_items.clear();
-    for (int i : e->big_ids) {
-        const BatchCirc& c = e->circs[i];
-        const Plan& p = e->plans[i];
-        for (int ps = 0; ps < c.npass; ++ps) {
-            const int L = p.hdrs[p.passes[ps].hdr].L;
-            const int nt = 1 << (p.n - L);
-            for (int t = 0; t < nt; ++t) e->pass_items[ps].push_back(BatchItem{i, t});
+    for (int ps = 0; ps < maxpass; ++ps) {
+        const size_t first = e->nodes.size();
+        for (int i : e->big_ids) {
+            const BatchCirc& c = e->circs[i];
+            const Plan& p = e->plans[i];
+            if (ps >= c.npass) continue;
+            const PassPlan& pp = p.passes[ps];
+            const PassHdr& h = p.hdrs[pp.hdr];
+            const int kind = pp.type == PASS_TILE_REG ? 0 : 1;
+            const int R = kind == 0 ? pp.R : 0, W = kind == 0 ? pp.W : 0;
+            size_t at = first;
+            while (at < e->nodes.size() &&
+                   !(e->nodes[at].kind == kind && e->nodes[at].R == R && e->nodes[at].W == W))
+                ++at;
+            if (at == e->nodes.size()) {
+                qops_batch_exec::Node nd;
+                nd.pass = ps;
+                nd.kind = kind;
+                nd.R = R;
+                nd.W = W;
+                e->nodes.push_back(nd);
+            }
+            qops_batch_exec::Node& nd = e->nodes[at];
+            const int need = kind == 0 ? h.lds_bytes
+                                       : (int)(((size_t)1 << h.L) * asz + (size_t)h.coef_n * csz);
+            nd.lds = std::max(nd.lds, (need + 15) & ~15);
+            const int nt = 1 << (p.n - pp.L);
+            for (int t = 0; t < nt; ++t) nd.items.push_back(BatchItem{i, t});
         }
+    }
+    for (const auto& nd : e->nodes)
+        if (nd.lds > 160 * 1024) return set_error(QOPS_UNSUPPORTED, "batch pass needs more LDS than a CU has");
+    for (int i : e->big_ids) {
+        const Plan& p = e->plans[i];
         const int s = std::min(p.n, 13);
         for (int t = 0; t < (1 << (p.n - s)); ++t) e->z_items.push_back(BatchItem{i, t});
     }
@@ -181,9 +214,8 @@ int32_t layout(qops_batch_exec* e)
         (er = up(e->d_big, e->big_ids.data(), e->big_ids.size() * sizeof(int32_t))) != hipSuccess ||
         (er = up(e->d_zitems, e->z_items.data(), e->z_items.size() * sizeof(BatchItem))) != hipSuccess)
         return hip_fail(er, "batch upload");
-    e->d_items.assign(maxpass, nullptr);
-    for (int ps = 0; ps < maxpass; ++ps)
-        if ((er = up(e->d_items[ps], e->pass_items[ps].data(), e->pass_items[ps].size() * sizeof(BatchItem))) != hipSuccess)
+    for (auto& nd : e->nodes)
+        if ((er = up(nd.d, nd.items.data(), nd.items.size() * sizeof(BatchItem))) != hipSuccess)
             return hip_fail(er, "batch upload");
     if ((er = hipMalloc((void**)&e->d_part, std::max<size_t>(e->total_part * QOPS_BATCH_REC, 1) * sizeof(double))) != hipSuccess ||
         (er = hipMalloc((void**)&e->d_out, std::max<size_t>(e->total_out, 1) * sizeof(double))) != hipSuccess)
@@ -195,9 +227,15 @@ hipError_t enqueue(qops_batch_exec* e, hipStream_t s)
 {
     hipError_t er = launch_batch_small(e->prec, e->d_small, (int)e->small_ids.size(), e->d_circs, e->d_ops, e->d_coef,
                                        e->d_out, e->lds_small, s);
-    for (size_t ps = 0; ps < e->pass_items.size() && er == hipSuccess; ++ps)
-        er = launch_batch_pass(e->prec, e->d_items[ps], (int)e->pass_items[ps].size(), e->d_circs, e->d_hdrs, e->d_ops,
-                               e->d_coef, (int)ps, e->lds_pass, e->grid, s);
+    for (size_t k = 0; k < e->nodes.size() && er == hipSuccess; ++k) {
+        const auto& nd = e->nodes[k];
+        if (nd.kind == 0)
+            er = launch_batch_reg(e->prec, nd.R, nd.W, nd.d, (int)nd.items.size(), e->d_circs, e->d_hdrs, e->d_ops,
+                                  e->d_coef, nd.pass, nd.lds, e->grid * 4, s);
+        else
+            er = launch_batch_pass(e->prec, nd.d, (int)nd.items.size(), e->d_circs, e->d_hdrs, e->d_ops, e->d_coef,
+                                   nd.pass, nd.lds, e->grid, s);
+    }
     if (er == hipSuccess)
         er = launch_batch_z(e->prec, e->d_zitems, (int)e->z_items.size(), e->d_big, (int)e->big_ids.size(), e->d_circs,
                             e->d_part, e->d_out, e->grid, s);
@@ -212,8 +250,8 @@ void release(qops_batch_exec* e)
                     e->d_states};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
-    for (BatchItem* p : e->d_items)
-        if (p) (void)hipFree(p);
+    for (auto& nd : e->nodes)
+        if (nd.d) (void)hipFree(nd.d);
     if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
 }
 
@@ -293,6 +331,17 @@ int32_t qops_batch_results(qops_batch_exec* e, double* out_expz)
     hipError_t er = hipMemcpyAsync(out_expz, e->d_out, e->total_out * sizeof(double), hipMemcpyDeviceToHost, e->stream);
     if (er == hipSuccess) er = hipStreamSynchronize(e->stream);
     if (er != hipSuccess) return hip_fail(er, "batch results");
+    // the kernels reduce per physical bit; logical qubit q sits at l2p[q]
+    std::vector<double> tmp;
+    for (int i = 0; i < e->count; ++i) {
+        const qops::Plan& p = e->plans[i];
+        double* o = out_expz + e->circs[i].out0;
+        bool ident = true;
+        for (int q = 0; q < p.n; ++q) ident = ident && p.l2p_out[q] == q;
+        if (ident) continue;
+        tmp.assign(o, o + p.n);
+        for (int q = 0; q < p.n; ++q) o[q] = tmp[p.l2p_out[q]];
+    }
     return QOPS_OK;
 }
 
@@ -350,7 +399,7 @@ int32_t qops_batch_info(const qops_batch_exec* e, qops_batch_stats* s)
     std::memset(s, 0, sizeof(*s));
     s->small_circuits = (int32_t)e->small_ids.size();
     s->tile_circuits = (int32_t)e->big_ids.size();
-    s->graph_nodes = (int32_t)(e->pass_items.size() + (e->small_ids.empty() ? 0 : 1) + (e->big_ids.empty() ? 0 : 2));
+    s->graph_nodes = (int32_t)(e->nodes.size() + (e->small_ids.empty() ? 0 : 1) + (e->big_ids.empty() ? 0 : 2));
     s->small_max_n = e->small_max_n;
     s->tile_bits = e->tile_bits;
     s->outputs = (int64_t)e->total_out;

@@ -577,24 +577,21 @@ __device__ __forceinline__ uint32_t reg_lds(const MapState<R, W>& ms, int j)
     return o;
 }
 
+// One tile of a register-tile pass: load, every operation of the pass,
+// store.  `lds` is the work-group's exchange buffer (wave bits), `fresh`
+// replaces the load by |0..0> (the first pass of a batched circuit).
 template <typename T, int R, int W>
-__global__ void __launch_bounds__(64 << W)
-tile_pass_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict__ hp, const DevOp* __restrict__ ops,
-                 const T* __restrict__ coef, uint64_t ntiles)
+__device__ __forceinline__ void reg_tile(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict__ hp,
+                                         const DevOp* __restrict__ ops, const T* __restrict__ coef, uint64_t tile,
+                                         typename CxT<T>::V* lds, int lane, int wave, bool fresh)
 {
     using V = typename CxT<T>::V;
     constexpr int NR = 1 << R;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    V* lds = reinterpret_cast<V*>(smem_raw);
-
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
     const int nops = hp->nops;
     const DevOp* __restrict__ prog = ops + hp->op0;
     const int nruns = hp->nruns;
     const int32_t* __restrict__ up_phys = hp->up_phys;
-
-    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    {
         uint64_t base = 0;
         for (int r = 0; r < nruns; ++r) {
             const uint64_t field = (tile >> hp->run_gshift[r]) & ((1ull << hp->run_len[r]) - 1ull);
@@ -603,7 +600,14 @@ tile_pass_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict_
         MapState<R, W> ms;
         set_map<R, W>(ms, (uint32_t)hp->map0, up_phys, lane, wave);
         V a[NR];
-        {
+        if (fresh) {
+            sfor<NR>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                const bool one = base + ms.tphys + reg_phys(ms, j) == 0;
+                a[j].x = one ? (T)1 : (T)0;
+                a[j].y = (T)0;
+            });
+        } else {
             const V* src = st + base + ms.tphys;
             sfor<NR>([&](auto jc) { a[decltype(jc)::value] = src[reg_phys(ms, decltype(jc)::value)]; });
         }
@@ -750,6 +754,40 @@ tile_pass_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict_
             V* dst = st + base + tp;
             sfor<NR>([&](auto jc) { dst[reg_phys(ms, decltype(jc)::value)] = a[decltype(jc)::value]; });
         }
+    }
+}
+
+template <typename T, int R, int W>
+__global__ void __launch_bounds__(64 << W)
+tile_pass_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict__ hp, const DevOp* __restrict__ ops,
+                 const T* __restrict__ coef, uint64_t ntiles)
+{
+    using V = typename CxT<T>::V;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    V* lds = reinterpret_cast<V*>(smem_raw);
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+        reg_tile<T, R, W>(st, hp, ops, coef, tile, lds, lane, wave, false);
+}
+
+// Batched executor: register-tile pass `pass` of every circuit in `items`
+// (all planned with the same register/wave split).
+template <typename T, int R, int W>
+__global__ void __launch_bounds__(64 << W)
+batch_reg_kernel(const BatchItem* __restrict__ items, int nitems, const BatchCirc* __restrict__ circs,
+                 const PassHdr* __restrict__ hdrs, const DevOp* __restrict__ ops, const T* __restrict__ coef, int pass)
+{
+    using V = typename CxT<T>::V;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    V* lds = reinterpret_cast<V*>(smem_raw);
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+        const BatchItem it = items[i];
+        const BatchCirc c = circs[it.c];
+        reg_tile<T, R, W>(reinterpret_cast<V*>(c.state), hdrs + c.hdr0 + pass, ops, coef, (uint64_t)it.tile, lds,
+                          lane, wave, pass == 0);
     }
 }
 
@@ -1760,6 +1798,36 @@ hipError_t launch_batch_pass(int prec, const BatchItem* items, int nitems, const
                            reinterpret_cast<const double*>(coef), pass);
     }
     return hipGetLastError();
+}
+
+template <typename T, int R, int W>
+static hipError_t launch_batch_reg_t(const BatchItem* items, int nitems, const BatchCirc* circs, const PassHdr* hdrs,
+                                     const DevOp* ops, const void* coef, int pass, int lds_bytes, int grid,
+                                     hipStream_t s)
+{
+    if (hipError_t e = hipFuncSetAttribute((const void*)batch_reg_kernel<T, R, W>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes))
+        return e;
+    const int g = std::max(1, std::min(nitems, grid));
+    hipLaunchKernelGGL((batch_reg_kernel<T, R, W>), dim3(g), dim3(64 << W), lds_bytes, s, items, nitems, circs, hdrs,
+                       ops, reinterpret_cast<const T*>(coef), pass);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_reg(int prec, int R, int W, const BatchItem* items, int nitems, const BatchCirc* circs,
+                            const PassHdr* hdrs, const DevOp* ops, const void* coef, int pass, int lds_bytes,
+                            int grid, hipStream_t s)
+{
+    if (nitems <= 0) return hipSuccess;
+#define QOPS_LAUNCH(r, w)                                                                                      \
+    if (R == r && W == w)                                                                                      \
+        return prec == 0 ? launch_batch_reg_t<float, r, w>(items, nitems, circs, hdrs, ops, coef, pass, lds_bytes,  \
+                                                           grid, s)                                           \
+                         : launch_batch_reg_t<double, r, w>(items, nitems, circs, hdrs, ops, coef, pass, lds_bytes, \
+                                                            grid, s);
+    QOPS_TILE_VARIANTS(QOPS_LAUNCH)
+#undef QOPS_LAUNCH
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_batch_z(int prec, const BatchItem* items, int nitems, const int32_t* ids, int count,

@@ -63,6 +63,10 @@ hipError_t launch_batch_small(int prec, const int32_t* ids, int count, const Bat
                               const void* coef, double* out, int lds_bytes, hipStream_t s);
 hipError_t launch_batch_pass(int prec, const BatchItem* items, int nitems, const BatchCirc* circs, const PassHdr* hdrs,
                              const DevOp* ops, const void* coef, int pass, int lds_bytes, int grid, hipStream_t s);
+// Batched register-tile pass `pass` over (circuit, tile) items of one R/W split.
+hipError_t launch_batch_reg(int prec, int R, int W, const BatchItem* items, int nitems, const BatchCirc* circs,
+                            const PassHdr* hdrs, const DevOp* ops, const void* coef, int pass, int lds_bytes,
+                            int grid, hipStream_t s);
 hipError_t launch_batch_z(int prec, const BatchItem* items, int nitems, const int32_t* ids, int count,
                           const BatchCirc* circs, double* part, double* out, int grid, hipStream_t s);
 int device_cus();

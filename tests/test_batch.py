@@ -95,3 +95,16 @@ def test_batch_edge_cases(q):
     z = b1.results()[0]
     assert abs(z[5] - np.cos(0.3)) < 1e-6 and np.allclose(np.delete(z, 5), 1.0)
     b1.close()
+
+
+@pytest.mark.gpu
+def test_batch_with_swaps_reports_logical_order(q):
+    """SWAPs are virtual: <Z_q> still comes back per logical qubit."""
+    c1 = W.layered_u3_cx(3, n=16, depth=6)          # contains SWAPs
+    c2 = W.layered_u3_cx(4, n=10, depth=6)
+    assert any(g.kind == "swap" for g in c1.gates)
+    b = q.Batch([(c1.n, c1.gates), (c2.n, c2.gates)], precision=1, small_max_n=11, tile_bits=12)
+    b.launch()
+    for c, z in zip((c1, c2), b.results()):
+        assert np.max(np.abs(z - orc.expect_z(orc.run_circuit(c)))) <= 1e-11
+    b.close()
