@@ -279,6 +279,130 @@ static bool merge_diag(LOp& y, const LOp& x)
     return true;
 }
 
+// Left-multiplies the block matrix M (2^|Q| square, row-major, index bit i
+// <-> physical bit Q[i]) by operation o embedded on the block's bits.
+static void block_apply(std::vector<cd>& M, const std::vector<int>& Q, const LOp& o)
+{
+    const int nb = (int)Q.size();
+    const uint32_t D = 1u << nb;
+    auto bpos = [&](int phys) {
+        for (int i = 0; i < nb; ++i)
+            if (Q[i] == phys) return i;
+        return -1;
+    };
+    uint32_t cm = 0;
+    for (int b = 0; b < 64; ++b)
+        if ((o.cmask >> b) & 1ull) cm |= 1u << bpos(b);
+    if (o.kind == LOp::DIAG) {
+        int tp[10];
+        for (int j = 0; j < o.k; ++j) tp[j] = bpos(o.t[j]);
+        for (uint32_t r = 0; r < D; ++r) {
+            if ((r & cm) != cm) continue;
+            uint32_t idx = 0;
+            for (int j = 0; j < o.k; ++j) idx |= ((r >> tp[j]) & 1u) << j;
+            const cd d = o.m[idx];
+            for (uint32_t c = 0; c < D; ++c) M[(size_t)r * D + c] *= d;
+        }
+        return;
+    }
+    const int k = o.kind == LOp::PSWAP ? 2 : o.k;
+    const uint32_t K = 1u << k;
+    uint32_t off[64], tmask = 0;
+    int tp[10];
+    for (int j = 0; j < k; ++j) {
+        tp[j] = bpos(o.t[j]);
+        tmask |= 1u << tp[j];
+    }
+    for (uint32_t s = 0; s < K; ++s) {
+        off[s] = 0;
+        for (int j = 0; j < k; ++j)
+            if (s & (1u << j)) off[s] |= 1u << tp[j];
+    }
+    std::vector<cd> in(K);
+    for (uint32_t r0 = 0; r0 < D; ++r0) {
+        if ((r0 & tmask) || (r0 & cm) != cm) continue;
+        for (uint32_t c = 0; c < D; ++c) {
+            for (uint32_t s = 0; s < K; ++s) in[s] = M[(size_t)(r0 | off[s]) * D + c];
+            for (uint32_t r = 0; r < K; ++r) {
+                cd acc = 0;
+                for (uint32_t s = 0; s < K; ++s) acc += o.m[(size_t)r * K + s] * in[s];
+                M[(size_t)(r0 | off[r]) * D + c] = acc;
+            }
+        }
+    }
+}
+
+// k-qubit block fusion: ops whose bits (targets, controls, table bits) fit a
+// common set of at most kmax physical bits become one dense 2^k x 2^k block,
+// the FP64 product of the ops embedded on that set.  Each block opens with
+// the first op not yet placed and scans ahead, taking ops that fit and
+// commute with every op skipped so far (the same rule as pass packing).
+// Blocks of a single op, and blocks of diagonals only, are kept as they are.
+static void fuse_blocks(std::vector<LOp>& ops, int kmax)
+{
+    if (kmax < 2) return;
+    const size_t n = ops.size();
+    const size_t window = 64;
+    std::vector<char> placed(n, 0);
+    std::vector<LOp> out;
+    out.reserve(n);
+    for (size_t first = 0; first < n; ++first) {
+        if (placed[first]) continue;
+        placed[first] = 1;
+        const LOp& a = ops[first];
+        if (a.dead) continue;
+        if (a.kind == LOp::PSWAP || __builtin_popcountll(a.touch()) > kmax) {
+            out.push_back(a);
+            continue;
+        }
+        uint64_t Qm = a.touch();
+        std::vector<size_t> mem = {first};
+        uint64_t skip_touch = 0, skip_nd = 0;
+        const size_t stop = std::min(n, first + 1 + window);
+        for (size_t j = first + 1; j < stop; ++j) {
+            if (placed[j] || ops[j].dead) continue;
+            const LOp& o = ops[j];
+            if (o.kind == LOp::PSWAP) break;
+            const uint64_t tj = o.touch(), nj = o.tmask();
+            const bool commutes = (nj & skip_touch) == 0 && (tj & skip_nd) == 0;
+            if (commutes && __builtin_popcountll(Qm | tj) <= kmax) {
+                Qm |= tj;
+                mem.push_back(j);
+                placed[j] = 1;
+            } else {
+                skip_touch |= tj;
+                skip_nd |= nj;
+            }
+        }
+        bool all_diag = true;
+        for (size_t j : mem) all_diag = all_diag && ops[j].kind == LOp::DIAG;
+        if (mem.size() == 1 || all_diag) {
+            for (size_t j : mem) out.push_back(ops[j]);
+            continue;
+        }
+        std::vector<int> Q;
+        for (int b = 0; b < 64; ++b)
+            if ((Qm >> b) & 1ull) Q.push_back(b);
+        const uint32_t D = 1u << Q.size();
+        LOp f;
+        f.kind = LOp::DENSE;
+        f.k = (int)Q.size();
+        for (int j = 0; j < f.k; ++j) f.t[j] = Q[j];
+        f.cmask = 0;
+        f.m.assign((size_t)D * D, cd(0));
+        for (uint32_t i = 0; i < D; ++i) f.m[(size_t)i * D + i] = 1;
+        f.gate = a.gate;
+        f.gkind = QOPS_DENSE;
+        f.nmerged = 0;
+        for (size_t j : mem) {
+            block_apply(f.m, Q, ops[j]);
+            f.nmerged += ops[j].nmerged;
+        }
+        out.push_back(std::move(f));
+    }
+    ops.swap(out);
+}
+
 static void merge_ops(std::vector<LOp>& in, std::vector<LOp>& out)
 {
     const int kScan = 96;
@@ -1061,10 +1185,12 @@ Err build_plan(int n, int prec, const int32_t* l2p_in, const qops_gate* g, size_
     e = lower(n, p.gates.data(), ng, par.swap_mode, l2p, lowered, p.n_virtual_swaps);
     if (!e.ok()) return e;
     p.l2p_out = l2p;
-    if (par.mode == QOPS_PLAN_GATEWISE)
+    if (par.mode == QOPS_PLAN_GATEWISE) {
         p.lops.swap(lowered);
-    else
+    } else {
         merge_ops(lowered, p.lops);
+        fuse_blocks(p.lops, std::min(par.max_fuse_k, 6));
+    }
     pack(p);
     p.dirty = true;
     p.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -159,3 +159,13 @@ def test_layout_calls(q):
     phys = sim.state(q.ORDER_PHYSICAL)
     assert np.array_equal(orc.logical_from_physical(phys, perm), before)
     sim.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("kmax", [3, 4, 5, 6])
+def test_fused_blocks(q, prec, kmax):
+    """Gates fused into dense k-qubit blocks (matrix cores for k >= 3) agree
+    with the gate-by-gate oracle."""
+    for c in (W.qft_then_layers(1, n=16, layers=4), W.random_mix_layers(9, 17, 6)):
+        got, l2p = run_gpu(q, c, prec, max_fuse_k=kmax)
+        check_state(got, orc.run_circuit(c), prec, f"{c.name} kmax={kmax}")

@@ -167,3 +167,37 @@ def test_plan_update_rebinds_parameters():
     bad[0] = W.Gate("rx", bad[0].qubits, (), bad[0].params)
     with pytest.raises(q.QopsError):
         plan.update(bad)
+
+
+@pytest.mark.parametrize("name,make", CASES)
+@pytest.mark.parametrize("kmax", [2, 3, 4, 6])
+def test_block_fusion_reproduces_circuit(name, make, kmax):
+    """Fused k-qubit blocks (FP64 products of the ops they absorb, ops moved
+    only past ops they commute with) reproduce the circuit."""
+    c = make()
+    plan = q.Plan(c.n, c.gates, precision=q.C128, max_fuse_k=kmax)
+    got = physical_replay(c.n, plan, c.x0)
+    ref = orc.run_circuit(c)
+    assert np.max(np.abs(got - ref)) <= 1e-12
+    ops = plan.ops()
+    assert all(o["k"] <= max(kmax, 6) for o in ops)
+    base = q.Plan(c.n, c.gates, precision=q.C128).ops()
+    assert len(ops) <= len(base)
+    assert sum(o["n_merged"] for o in ops) == sum(o["n_merged"] for o in base)
+
+
+def test_block_fusion_counts():
+    n = 12
+    # ten 1q gates and three CZ on qubits {2,3,4}: one 3-qubit block
+    gates = []
+    for r in range(3):
+        gates += [("u3", (2,), (0.1 * r, 0.2, 0.3)), ("u3", (3,), (0.3, 0.1 * r, 0.2)), ("rx", (4,), (0.4,))]
+        gates += [("cz", (2, 3))]
+    gates += [("ry", (4,), (0.7,))]
+    ops = q.Plan(n, gates, max_fuse_k=3).ops()
+    assert len(ops) == 1 and ops[0]["k"] == 3 and ops[0]["kind"] == 2
+    assert ops[0]["n_merged"] == len(gates)
+    # CX(4,7) leaves the 3-qubit set; the later H on 2 commutes with it and
+    # still joins the block
+    ops4 = q.Plan(n, gates + [("cx", (4, 7)), ("h", (2,))], max_fuse_k=3).ops()
+    assert len(ops4) == 2
