@@ -202,7 +202,7 @@ def main() -> None:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-learned-eval", action="store_true")
-    ap.add_argument("--eval-circuits", type=int, default=2)
+    ap.add_argument("--eval-circuits", type=int, default=10)
     ap.add_argument("--no-batch-eval", action="store_true")
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--dump-passes", default="", help="write the last step's pass records (JSON) here")

@@ -143,10 +143,12 @@ typedef struct qops_plan_opts {
     int32_t swap_mode;     /* enum qops_swap_mode (default VIRTUAL)           */
     int32_t tile_upper;    /* upper tile qubits per pass beyond the 6 lane
                               qubits; 0 = choose automatically                */
-    int32_t max_fuse_k;    /* widest dense block the planner may build by
-                              composing gates (1 = only 1q merging); 0 = auto */
-    int32_t use_mfma;      /* 1 = matrix cores for dense blocks with k >= 4
-                              (default), 0 = vector ALU only                  */
+    int32_t max_fuse_k;    /* widest dense block (<= 6 qubits) the planner
+                              may build by composing gates whose bits fit a
+                              common set (1 = only 1q merging); 0 = 1 in FUSED
+                              mode, chosen among 1..4 by PROFILED / LEARNED   */
+    int32_t use_mfma;      /* 1 = matrix cores for dense blocks with k >= 3
+                              (default), 0 = vector ALU where it can         */
     int32_t check_unitary; /* 1 = reject non-unitary DENSE input (1e-9)       */
     int32_t remap;         /* 1 = before the gates, move the six qubits that
                               non-diagonal gates target most often into
@@ -269,9 +271,11 @@ int32_t qops_profile_merge(qops_profile* dst, const qops_profile* src);
 int32_t qops_profile_free(qops_profile* pr);
 
 /* ------------------------------------------------------ cost model ---- */
-/* A 3-layer perceptron, 64 -> 128 -> 128 -> 1 with ReLU, predicting the
- * natural log of a pass's run time (seconds) from the 64 pass features of
- * qops_profile_features.  Parameters (float) in this order: W1 [128 x 64]
+/* A 3-layer perceptron, 64 -> 128 -> 128 -> 1 with ReLU, predicting from the
+ * 64 pass features of qops_profile_features the natural log of a pass's run
+ * time (seconds) scaled to 30 qubits: ln(t) - (n - 30) ln 2 for an n-qubit
+ * state (plan pricing adds the (n - 30) ln 2 back, so the per-amplitude cost
+ * it learns carries over to other sizes).  Parameters (float) in this order: W1 [128 x 64]
  * row-major, b1 [128], W2 [128 x 128], b2 [128], W3 [1 x 128], b3 [1];
  * inputs are standardised with per-feature mean/sd before the first layer.
  * Training runs on the GPU (forward, backward of the mean squared error,
@@ -290,7 +294,7 @@ int32_t qops_mlp_grad(qops_model* m, const float* X, const float* t, int32_t row
  * rows in batches of `batch`, reshuffled each epoch from `seed`.  Blocking. */
 int32_t qops_mlp_train(qops_model* m, const float* X, const float* t, int32_t rows, int32_t epochs, int32_t batch,
                        float lr, uint64_t seed, float* final_loss);
-/* out[r] = predicted log seconds of row r (on the GPU).  Blocking. */
+/* out[r] = the network's output for row r (on the GPU).  Blocking. */
 int32_t qops_mlp_predict(qops_model* m, const float* X, int32_t rows, float* out);
 int32_t qops_model_save(const qops_model* m, const char* path);
 int32_t qops_model_load(const char* path, qops_model** out);

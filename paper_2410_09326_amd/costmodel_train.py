@@ -3,8 +3,9 @@ cost model on the GPU.
 
 Corpus: seeded random circuits of 20..30 qubits (U3 / CZ / SWAP / RZZ
 layers, depth 20..100), each planned under a randomly drawn candidate (tile
-width 4..7, qubit remap on/off) and executed once as a profiling run; every
-fused pass is one sample (64 features -> log seconds).  Circuits are split
+width 4..7, qubit remap on/off, block fusion width 1..4) and executed once as
+a profiling run; every
+fused pass is one sample (64 features -> log seconds, scaled to 30 qubits).  Circuits are split
 90/10 into training and held-out sets.  The plain cost table is the
 least-squares fit the library makes to the training profile; the learned one
 is the perceptron trained here.  Both are scored on the held-out passes.
@@ -48,7 +49,8 @@ def collect(n_circuits: int, seed0: int = 1000, time_budget: float = 240.0, max_
             continue
         up = int(rng.integers(4, 8))
         remap = int(rng.integers(0, 2))
-        plan = q.Plan(c.n, c.gates, precision=q.C64, tile_upper=up, remap=remap)
+        kf = int(rng.integers(1, 5))
+        plan = q.Plan(c.n, c.gates, precision=q.C64, tile_upper=up, remap=remap, max_fuse_k=kf)
         if c.n not in sims:
             for k in list(sims):
                 sims.pop(k).close()
@@ -98,7 +100,9 @@ def main() -> None:
     os.makedirs(args.out, exist_ok=True)
     X, y, cid, ns, train_prof, hold_prof, done = collect(args.circuits, time_budget=args.time_budget)
     held = (cid % 10) == 9
-    Xtr, ytr = X[~held], y[~held]
+    # the network learns ln(t) scaled to 30 qubits (plan pricing scales back)
+    yn = y - (ns - 30) * np.log(2.0)
+    Xtr, ytr = X[~held], yn[~held]
     mu = Xtr.mean(axis=0)
     sd = Xtr.std(axis=0)
     sd[sd < 1e-6] = 1.0

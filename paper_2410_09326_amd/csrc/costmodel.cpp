@@ -81,6 +81,13 @@ double plain_predict(const std::vector<double>& theta, const float* f)
     return std::max(y * scale, floor_s);
 }
 
+// The network predicts ln(seconds) scaled to 30 qubits; f[0] is n / 32.
+static double learned_seconds(float y, const float* f)
+{
+    const double n = std::round((double)f[0] * 32.0);
+    return std::exp((double)y + (n - 30.0) * 0.69314718055994530942);
+}
+
 static double price(const Plan& p, const qops_plan_opts* o, const std::vector<double>& theta)
 {
     std::vector<float> f(p.passes.size() * kNumFeatures);
@@ -89,7 +96,7 @@ static double price(const Plan& p, const qops_plan_opts* o, const std::vector<do
     if (o->mode == QOPS_PLAN_LEARNED && o->model) {
         std::vector<float> y(p.passes.size());
         mlp_predict_host(o->model, f.data(), (int)p.passes.size(), y.data());
-        for (float v : y) t += std::exp((double)v);
+        for (size_t i = 0; i < p.passes.size(); ++i) t += learned_seconds(y[i], &f[i * kNumFeatures]);
     } else {
         for (size_t i = 0; i < p.passes.size(); ++i) t += plain_predict(theta, &f[i * kNumFeatures]);
     }
@@ -114,24 +121,30 @@ int32_t build_priced_plan(int n, int prec, const int32_t* l2p, const qops_gate* 
     }
     const auto t0 = std::chrono::steady_clock::now();
     double best = -1;
+    // candidates: tile width above the six lane bits x qubit remap x block
+    // fusion width (a fixed fusion width in the options is kept)
     const int max_up = prec == QOPS_C64 ? 7 : 6;
-    for (int remap = 0; remap <= 1; ++remap)
-        for (int up = 4; up <= max_up; ++up) {
-            qops_plan_opts o = *opts;
-            o.tile_upper = up;
-            PlanParams cp = params_from(&o, n, prec);
-            cp.mode = QOPS_PLAN_FUSED;
-            cp.remap = remap;
-            Plan cand;
-            Err e = build_plan(n, prec, l2p, g, ng, cp, cand);
-            if (!e.ok()) return set_error(e.code, e.msg);
-            const double t = price(cand, opts, theta);
-            if (best < 0 || t < best) {
-                best = t;
-                out = std::move(cand);
-                out.predicted_s = t;
+    const int k_lo = opts->max_fuse_k > 0 ? opts->max_fuse_k : 1;
+    const int k_hi = opts->max_fuse_k > 0 ? opts->max_fuse_k : 4;
+    for (int kf = k_lo; kf <= k_hi; ++kf)
+        for (int remap = 0; remap <= 1; ++remap)
+            for (int up = 4; up <= max_up; ++up) {
+                qops_plan_opts o = *opts;
+                o.tile_upper = up;
+                o.max_fuse_k = kf;
+                PlanParams cp = params_from(&o, n, prec);
+                cp.mode = QOPS_PLAN_FUSED;
+                cp.remap = remap;
+                Plan cand;
+                Err e = build_plan(n, prec, l2p, g, ng, cp, cand);
+                if (!e.ok()) return set_error(e.code, e.msg);
+                const double t = price(cand, opts, theta);
+                if (best < 0 || t < best) {
+                    best = t;
+                    out = std::move(cand);
+                    out.predicted_s = t;
+                }
             }
-        }
     out.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return QOPS_OK;
 }
@@ -161,7 +174,7 @@ int32_t qops_profile_predict_passes(const qops_profile* pr, const qops_plan_opts
     if (opts->mode == QOPS_PLAN_LEARNED && opts->model) {
         std::vector<float> y(np);
         qops::mlp_predict_host(opts->model, pr->feats.data(), (int)np, y.data());
-        for (size_t i = 0; i < np; ++i) out[i] = std::exp((double)y[i]);
+        for (size_t i = 0; i < np; ++i) out[i] = qops::learned_seconds(y[i], &pr->feats[i * qops::kNumFeatures]);
         return QOPS_OK;
     }
     std::vector<double> theta;

@@ -76,3 +76,45 @@ def test_training_reduces_loss_and_predicts(q):
     m2 = q.CostModel(W.mlp_init(5).astype(np.float32))
     m2.train(X, t, epochs=30, batch=128, lr=2e-3, seed=1)
     assert np.array_equal(m2.params()[0], p)
+
+
+@pytest.mark.gpu
+def test_learned_model_gains_over_plain_table(q):
+    """The shipped network (trained on the GPU from profiling runs) against
+    the plain cost table fitted to the shipped profile, on passes of fresh
+    circuits it never saw: its per-pass time predictions are closer, and the
+    plans it picks compute the same result."""
+    here = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    models = os.path.join(here, "paper_2410_09326_amd", "models")
+    model = q.CostModel.load(os.path.join(models, "cost_mlp.bin"))
+    prof = q.Profile.load(os.path.join(models, "corpus_profile.bin"))
+    rng = np.random.default_rng(77)
+    true, p_learned, p_plain = [], [], []
+    for seed in range(30000, 30006):
+        c = W.corpus_circuit(seed, n_override=int(rng.integers(20, 25)))
+        plan = q.Plan(c.n, c.gates, precision=q.C64, tile_upper=int(rng.integers(4, 8)),
+                      remap=int(rng.integers(0, 2)), max_fuse_k=int(rng.integers(1, 5)))
+        sim = q.Simulator(c.n, q.C64)
+        sim.init_basis(0)
+        sim.run(plan)                      # warm
+        sim.init_basis(0)
+        pr = sim.profile(plan)
+        sim.close()
+        true.append(np.array([r["seconds"] for r in pr.records()]))
+        p_learned.append(pr.predict_passes(mode=q.PLAN_LEARNED, model=model))
+        p_plain.append(pr.predict_passes(mode=q.PLAN_PROFILED, profile=prof))
+    t = np.concatenate(true)
+    mape_l = float(np.mean(np.abs(np.concatenate(p_learned) - t) / t))
+    mape_p = float(np.mean(np.abs(np.concatenate(p_plain) - t) / t))
+    print(f"held-out passes {t.size}: MAPE learned {mape_l:.3f}, plain table {mape_p:.3f}")
+    assert mape_l < mape_p and mape_l < 0.25
+    # both pricings pick plans that compute the same <Z>
+    c = W.eval_circuit(9100, n=22, depth=20)
+    zs = []
+    for mode, kw in ((q.PLAN_LEARNED, {"model": model}), (q.PLAN_PROFILED, {"profile": prof})):
+        sim = q.Simulator(c.n, q.C64)
+        sim.init_basis(0)
+        sim.run(q.Plan(c.n, c.gates, precision=q.C64, mode=mode, **kw))
+        zs.append(sim.expect_z())
+        sim.close()
+    assert np.max(np.abs(zs[0] - zs[1])) <= 1e-5
