@@ -30,6 +30,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 MFMA_F32_PEAK_TFLOPS = 157.3
 MFMA_F64_PEAK_TFLOPS = 78.6
+# vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz, the
+# rate of unpacked FP32 and of FP64 FMAs (the library builds without packed
+# FP32 instructions)
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+MATRIX_KERNELS = ("tile_lds_kernel", "state_lds_kernel")
 PASS_NAMES = {0: "tile_pass_kernel", 1: "tile_lds_kernel", 2: "state_lds_kernel", 3: "sweep_kernel",
               4: "swap_bits_kernel"}
 
@@ -153,7 +158,8 @@ def batch_sweep(reps: int):
     """The parameter-sweep batch: 512 circuits of 10..22 qubits (RY/RZ layers
     plus a CZ ladder, depth 8..32, seed 5) in complex64, all in one graph
     launch producing <Z_i> for every qubit of every circuit.  The autotuner
-    picks the whole-state-in-LDS cut-off and the tile width first.  A sample
+    picks the whole-state-in-LDS cut-off, the tile width and the block fusion
+    width first.  A sample
     of eight circuits is re-run one at a time in complex128 on the
     single-circuit path to state the batch's max-abs error."""
     import tempfile
@@ -164,10 +170,10 @@ def batch_sweep(reps: int):
     spec = [(c.n, q.GateArray(c.gates)) for c in circs]
     cache = os.path.join(tempfile.gettempdir(), "qops_batch_tune.txt")
     t0 = time.perf_counter()
-    sm, tb, _ = q.Batch.autotune(spec, precision=q.C64, cache=cache)
+    sm, tb, kf, _ = q.Batch.autotune(spec, precision=q.C64, cache=cache)
     tune_s = time.perf_counter() - t0
     t0 = time.perf_counter()
-    b = q.Batch(spec, precision=q.C64, small_max_n=sm, tile_bits=tb)
+    b = q.Batch(spec, precision=q.C64, small_max_n=sm, tile_bits=tb, max_fuse_k=kf)
     create_s = time.perf_counter() - t0
     info = b.info()
     b.launch()
@@ -187,7 +193,7 @@ def batch_sweep(reps: int):
                         "(seed 5), complex64, one graph launch, <Z_i> of every qubit",
             "circuits_per_s": round(len(circs) / sec, 1), "launch_ms": round(sec * 1e3, 3),
             "gates": int(sum(len(c.gates) for c in circs)),
-            "autotuned": {"small_max_n": sm, "tile_bits": tb, "tune_s": round(tune_s, 2)},
+            "autotuned": {"small_max_n": sm, "tile_bits": tb, "max_fuse_k": kf, "tune_s": round(tune_s, 2)},
             "create_s": round(create_s, 2), "small_circuits": info["small_circuits"],
             "tile_circuits": info["tile_circuits"], "graph_kernel_nodes": info["graph_nodes"],
             "max_abs_vs_c128_sample": err}
@@ -274,9 +280,12 @@ def main() -> None:
     flops_launch = d["flops"] / d["launches"]
     gbs = bytes_launch / avg_s / 1e9
     tfl = flops_launch / avg_s / 1e12
-    fpeak = MFMA_F32_PEAK_TFLOPS if prec == q.C64 else MFMA_F64_PEAK_TFLOPS
+    if dom in MATRIX_KERNELS:
+        cbound, fpeak = "mfma", (MFMA_F32_PEAK_TFLOPS if prec == q.C64 else MFMA_F64_PEAK_TFLOPS)
+    else:
+        cbound, fpeak = "alu", round(VALU_PEAK_TFLOPS, 1)
     if tfl / fpeak > gbs / HBM_PEAK_GBS:
-        roof = {"bound": "mfma", "achieved": round(tfl, 2), "peak": fpeak, "unit": "TFLOP/s",
+        roof = {"bound": cbound, "achieved": round(tfl, 2), "peak": fpeak, "unit": "TFLOP/s",
                 "frac": round(tfl / fpeak, 4)}
     else:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -333,6 +333,8 @@ typedef struct qops_batch {
     int32_t small_max_n;           /* whole-state-in-LDS limit (0 = 13 / 12)    */
     int32_t tile_bits;             /* tile size 2^tile_bits of the larger ones
                                       (0 = 13 / 12)                             */
+    int32_t max_fuse_k;            /* block fusion width (as in qops_plan_opts;
+                                      0 = 1)                                    */
 } qops_batch;
 typedef struct qops_batch_exec qops_batch_exec;
 typedef struct qops_batch_stats {
@@ -341,6 +343,7 @@ typedef struct qops_batch_stats {
     int32_t graph_nodes;
     int32_t small_max_n;
     int32_t tile_bits;
+    int32_t max_fuse_k;
     int64_t outputs;
     double state_bytes;            /* device memory of the tile-pass states     */
 } qops_batch_stats;
@@ -359,11 +362,12 @@ int32_t qops_batch_time(qops_batch_exec* e, int32_t reps, double* seconds);
 int32_t qops_batch_update(qops_batch_exec* e, const qops_gate* const* gates, const size_t* n_gates);
 int32_t qops_batch_info(const qops_batch_exec* e, qops_batch_stats* s);
 int32_t qops_batch_free(qops_batch_exec* e);
-/* Autotuner: times the batch for every (small_max_n, tile_bits) candidate
- * and returns the fastest; results are cached in a text file keyed by the
- * batch's precision, size and qubit-count histogram (cache_path nullable). */
+/* Autotuner: times the batch for every (small_max_n, tile_bits, max_fuse_k)
+ * candidate and returns the fastest; results are cached in a text file keyed
+ * by the batch's precision, size and qubit-count histogram (cache_path
+ * nullable).  b's own shape fields are ignored. */
 int32_t qops_batch_autotune(const qops_batch* b, const char* cache_path, int32_t* best_small_max_n,
-                            int32_t* best_tile_bits, double* best_seconds);
+                            int32_t* best_tile_bits, int32_t* best_fuse_k, double* best_seconds);
 
 /* ------------------------------------------------------------ layout ---- */
 /* SWAP of logical qubits a and b.  VIRTUAL: exchange l2p[a] and l2p[b], move

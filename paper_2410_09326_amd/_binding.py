@@ -70,12 +70,13 @@ class BatchDesc(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int32), ("n", ctypes.POINTER(ctypes.c_int32)),
                 ("gates", ctypes.POINTER(ctypes.POINTER(Gate))), ("n_gates", ctypes.POINTER(ctypes.c_size_t)),
                 ("precision", ctypes.c_int32), ("stream", ctypes.c_void_p), ("small_max_n", ctypes.c_int32),
-                ("tile_bits", ctypes.c_int32)]
+                ("tile_bits", ctypes.c_int32), ("max_fuse_k", ctypes.c_int32)]
 
 
 class BatchStats(ctypes.Structure):
     _fields_ = [("small_circuits", ctypes.c_int32), ("tile_circuits", ctypes.c_int32),
                 ("graph_nodes", ctypes.c_int32), ("small_max_n", ctypes.c_int32), ("tile_bits", ctypes.c_int32),
+                ("max_fuse_k", ctypes.c_int32),
                 ("outputs", ctypes.c_int64), ("state_bytes", ctypes.c_double)]
 
 
@@ -143,7 +144,7 @@ SIGNATURES = {
     "qops_batch_update": (_I32, [_VP, ctypes.POINTER(ctypes.POINTER(Gate)), ctypes.POINTER(ctypes.c_size_t)]),
     "qops_batch_info": (_I32, [_VP, ctypes.POINTER(BatchStats)]),
     "qops_batch_free": (_I32, [_VP]),
-    "qops_batch_autotune": (_I32, [ctypes.POINTER(BatchDesc), ctypes.c_char_p, _IP, _IP, _DP]),
+    "qops_batch_autotune": (_I32, [ctypes.POINTER(BatchDesc), ctypes.c_char_p, _IP, _IP, _IP, _DP]),
     "qops_swap": (_I32, [_VP, _I32, _I32, _I32]),
     "qops_get_layout": (_I32, [_VP, _IP]),
     "qops_set_layout": (_I32, [_VP, _IP]),
@@ -489,30 +490,31 @@ class Batch:
     """Many circuits (each given as (n, gates)) simulated from |0..0> in one
     graph launch; results are <Z_q> per circuit."""
 
-    def __init__(self, circuits, precision: int = C64, small_max_n: int = 0, tile_bits: int = 0) -> None:
+    def __init__(self, circuits, precision: int = C64, small_max_n: int = 0, tile_bits: int = 0,
+                 max_fuse_k: int = 0) -> None:
         self.ns = [int(n) for n, _ in circuits]
-        self._desc, self._keep = self._describe(circuits, precision, small_max_n, tile_bits)
+        self._desc, self._keep = self._describe(circuits, precision, small_max_n, tile_bits, max_fuse_k)
         h = ctypes.c_void_p()
         check(lib().qops_batch_create(ctypes.byref(self._desc), ctypes.byref(h)))
         self.handle = h
 
     @staticmethod
-    def _describe(circuits, precision, small_max_n, tile_bits):
+    def _describe(circuits, precision, small_max_n, tile_bits, max_fuse_k=0):
         arrays = [g if isinstance(g, GateArray) else GateArray(g) for _, g in circuits]
         cnt = len(arrays)
         ns = (ctypes.c_int32 * cnt)(*[int(n) for n, _ in circuits])
         gp = (ctypes.POINTER(Gate) * cnt)(*[a.ptr() for a in arrays])
         ng = (ctypes.c_size_t * cnt)(*[a.n for a in arrays])
-        d = BatchDesc(cnt, ns, gp, ng, precision, None, small_max_n, tile_bits)
+        d = BatchDesc(cnt, ns, gp, ng, precision, None, small_max_n, tile_bits, max_fuse_k)
         return d, (arrays, ns, gp, ng)
 
     @staticmethod
     def autotune(circuits, precision: int = C64, cache: Optional[str] = None):
         d, keep = Batch._describe(circuits, precision, 0, 0)
-        sm, tb, sec = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        sm, tb, kf, sec = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
         check(lib().qops_batch_autotune(ctypes.byref(d), cache.encode() if cache else None, ctypes.byref(sm),
-                                        ctypes.byref(tb), ctypes.byref(sec)))
-        return sm.value, tb.value, sec.value
+                                        ctypes.byref(tb), ctypes.byref(kf), ctypes.byref(sec)))
+        return sm.value, tb.value, kf.value, sec.value
 
     def close(self) -> None:
         if getattr(self, "handle", None):

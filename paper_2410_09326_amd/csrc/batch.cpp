@@ -23,7 +23,7 @@ using namespace qops;
 struct qops_batch_exec {
     int prec = 0;
     int count = 0;
-    int small_max_n = 0, tile_bits = 0;
+    int small_max_n = 0, tile_bits = 0, fuse_k = 1;
     std::vector<int> n;
     std::vector<qops::Plan> plans;
     std::vector<BatchCirc> circs;
@@ -70,6 +70,7 @@ int32_t plan_all(qops_batch_exec* e, const qops_batch* b)
         if (n < 1 || n > 26) return set_error(QOPS_UNSUPPORTED, "batch circuits need 1 <= n <= 26");
         PlanParams par = params_from(nullptr, n, b->precision);
         par.state_lds_max_n = e->small_max_n;
+        par.max_fuse_k = e->fuse_k;
         par.L_lds = std::min(e->tile_bits, n);
         // register tiles of the same width: R register bits, the rest wave bits
         par.W = std::max(0, std::min(2, std::min(e->tile_bits, n) - 6 - par.R));
@@ -274,6 +275,7 @@ int32_t qops_batch_create(const qops_batch* b, qops_batch_exec** out)
         e->tile_bits = b->tile_bits > 0 ? std::min(b->tile_bits, lds_cap) : lds_cap;
         if (e->tile_bits > e->small_max_n + 1) e->tile_bits = e->small_max_n + 1;
         if (e->tile_bits < 10) e->tile_bits = 10;
+        e->fuse_k = b->max_fuse_k > 0 ? std::min(b->max_fuse_k, 6) : 1;
         int32_t rc = plan_all(e.get(), b);
         if (rc) return rc;
         rc = layout(e.get());
@@ -402,6 +404,7 @@ int32_t qops_batch_info(const qops_batch_exec* e, qops_batch_stats* s)
     s->graph_nodes = (int32_t)(e->nodes.size() + (e->small_ids.empty() ? 0 : 1) + (e->big_ids.empty() ? 0 : 2));
     s->small_max_n = e->small_max_n;
     s->tile_bits = e->tile_bits;
+    s->max_fuse_k = e->fuse_k;
     s->outputs = (int64_t)e->total_out;
     s->state_bytes = (double)e->total_state_bytes;
     return QOPS_OK;
@@ -417,9 +420,9 @@ int32_t qops_batch_free(qops_batch_exec* e)
 }
 
 int32_t qops_batch_autotune(const qops_batch* b, const char* cache_path, int32_t* best_small_max_n,
-                            int32_t* best_tile_bits, double* best_seconds)
+                            int32_t* best_tile_bits, int32_t* best_fuse_k, double* best_seconds)
 {
-    if (!b || !best_small_max_n || !best_tile_bits) return set_error(QOPS_INVALID_ARG, "null argument");
+    if (!b || !best_small_max_n || !best_tile_bits || !best_fuse_k) return set_error(QOPS_INVALID_ARG, "null argument");
     // signature of the batch: size, precision, histogram of n
     int hist[27] = {0};
     for (int i = 0; i < b->count; ++i) hist[std::max(0, std::min(26, b->n[i]))]++;
@@ -431,12 +434,13 @@ int32_t qops_batch_autotune(const qops_batch* b, const char* cache_path, int32_t
             char line[4096];
             while (std::fgets(line, sizeof(line), f)) {
                 char key[4000];
-                int sm = 0, tb = 0;
+                int sm = 0, tb = 0, kf = 0;
                 double sec = 0;
-                if (std::sscanf(line, "%3999s %d %d %lf", key, &sm, &tb, &sec) == 4 && sig == key) {
+                if (std::sscanf(line, "%3999s %d %d %d %lf", key, &sm, &tb, &kf, &sec) == 5 && sig == key) {
                     std::fclose(f);
                     *best_small_max_n = sm;
                     *best_tile_bits = tb;
+                    *best_fuse_k = kf;
                     if (best_seconds) *best_seconds = sec;
                     return QOPS_OK;
                 }
@@ -446,12 +450,14 @@ int32_t qops_batch_autotune(const qops_batch* b, const char* cache_path, int32_t
     }
     const int cap = b->precision == QOPS_C64 ? 13 : 12;
     double best = -1;
+    for (int kf = 1; kf <= 3; ++kf)
     for (int sm = 10; sm <= cap; ++sm)
         for (int tb = 11; tb <= cap; ++tb) {
             if (tb > sm + 1) continue;     // the executor would clamp it to sm + 1
             qops_batch bb = *b;
             bb.small_max_n = sm;
             bb.tile_bits = tb;
+            bb.max_fuse_k = kf;
             qops_batch_exec* e = nullptr;
             int32_t rc = qops_batch_create(&bb, &e);
             if (rc) return rc;
@@ -464,12 +470,13 @@ int32_t qops_batch_autotune(const qops_batch* b, const char* cache_path, int32_t
                 best = sec;
                 *best_small_max_n = sm;
                 *best_tile_bits = tb;
+                *best_fuse_k = kf;
             }
         }
     if (best_seconds) *best_seconds = best;
     if (cache_path)
         if (FILE* f = std::fopen(cache_path, "a")) {
-            std::fprintf(f, "%s %d %d %.9g\n", sig.c_str(), *best_small_max_n, *best_tile_bits, best);
+            std::fprintf(f, "%s %d %d %d %.9g\n", sig.c_str(), *best_small_max_n, *best_tile_bits, *best_fuse_k, best);
             std::fclose(f);
         }
     return QOPS_OK;

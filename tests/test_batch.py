@@ -53,6 +53,18 @@ def test_batch_matches_oracle(q, prec, tol):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("kf", [2, 3])
+def test_batch_fused_blocks(q, kf):
+    circs = small_batch(seed=8, count=10)
+    b = q.Batch([(c.n, c.gates) for c in circs], precision=1, small_max_n=11, tile_bits=12, max_fuse_k=kf)
+    assert b.info()["max_fuse_k"] == kf
+    b.launch()
+    for c, z in zip(circs, b.results()):
+        assert np.max(np.abs(z - orc.expect_z(orc.run_circuit(c)))) <= 1e-11
+    b.close()
+
+
+@pytest.mark.gpu
 def test_batch_parameter_update(q):
     circs = small_batch(seed=6, count=10)
     b = q.Batch([(c.n, c.gates) for c in circs], precision=1, small_max_n=10, tile_bits=10)
@@ -70,10 +82,10 @@ def test_batch_parameter_update(q):
 def test_batch_autotune(q, tmp_path):
     circs = small_batch(seed=7, count=8, nmin=10, nmax=14)
     cache = str(tmp_path / "tune.txt")
-    sm, tb, sec = q.Batch.autotune([(c.n, c.gates) for c in circs], precision=0, cache=cache)
-    assert 10 <= sm <= 13 and 11 <= tb <= 13 and sec > 0
-    sm2, tb2, sec2 = q.Batch.autotune([(c.n, c.gates) for c in circs], precision=0, cache=cache)
-    assert (sm2, tb2) == (sm, tb)
+    sm, tb, kf, sec = q.Batch.autotune([(c.n, c.gates) for c in circs], precision=0, cache=cache)
+    assert 10 <= sm <= 13 and 11 <= tb <= 13 and 1 <= kf <= 3 and sec > 0
+    sm2, tb2, kf2, sec2 = q.Batch.autotune([(c.n, c.gates) for c in circs], precision=0, cache=cache)
+    assert (sm2, tb2, kf2) == (sm, tb, kf)
 
 
 @pytest.mark.gpu
