@@ -212,6 +212,7 @@ def main() -> None:
     ap.add_argument("--no-batch-eval", action="store_true")
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--dump-passes", default="", help="write the last step's pass records (JSON) here")
+    ap.add_argument("--trace", default="", help="write the last step's profile as a Chrome trace here")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 2^30 x 8-byte device copy (counter calibration)")
     args = ap.parse_args()
@@ -246,6 +247,7 @@ def main() -> None:
         sim.init_basis(circ.x0)
         prof = sim.profile(plan)          # the plan, with HIP events around every pass
         recs_all.append(prof.records())
+        last_prof = prof
         z = sim.expect_z()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
@@ -259,6 +261,8 @@ def main() -> None:
         torch.cuda.synchronize()
         del a, b
 
+    if args.trace:
+        last_prof.trace(args.trace)
     if args.dump_passes:
         with open(args.dump_passes, "w") as fh:
             json.dump({"passes": passes, "records": recs_all[-1]}, fh)

@@ -265,6 +265,13 @@ int32_t qops_profile_total(const qops_profile* pr, double* seconds, int32_t* n);
 int32_t qops_profile_features(const qops_profile* pr, float* out);
 /* Writes the profile (counters, pass records) as JSON. */
 int32_t qops_profile_dump(const qops_profile* pr, const char* path);
+/* Writes the profile as a Chrome trace-event file (the JSON that
+ * chrome://tracing and Perfetto open): one complete event per pass on a
+ * "passes" track (start, duration, kernel kind, tile bits, operations, gates,
+ * algorithmic bytes and flops, achieved GB/s), and per logical qubit a
+ * counter track of the gates that touch it (the per-qubit hotspot view of
+ * the paper's performance-debug use, Sec. IV-D). */
+int32_t qops_profile_trace(const qops_profile* pr, const char* path);
 /* Merges the pass records of `src` into `dst` (a cost table built from many
  * profiling runs). */
 int32_t qops_profile_merge(qops_profile* dst, const qops_profile* src);

@@ -117,6 +117,7 @@ SIGNATURES = {
     "qops_profile_total": (_I32, [_VP, _DP, _IP]),
     "qops_profile_features": (_I32, [_VP, ctypes.POINTER(ctypes.c_float)]),
     "qops_profile_dump": (_I32, [_VP, ctypes.c_char_p]),
+    "qops_profile_trace": (_I32, [_VP, ctypes.c_char_p]),
     "qops_profile_merge": (_I32, [_VP, _VP]),
     "qops_profile_free": (_I32, [_VP]),
     "qops_profile_create": (_I32, [_I32, ctypes.POINTER(_VP)]),
@@ -375,6 +376,10 @@ class Profile:
 
     def dump(self, path: str) -> None:
         check(lib().qops_profile_dump(self.handle, path.encode()))
+
+    def trace(self, path: str) -> None:
+        """Chrome trace-event JSON of the passes and per-qubit gate counts."""
+        check(lib().qops_profile_trace(self.handle, path.encode()))
 
     def merge(self, other: "Profile") -> None:
         check(lib().qops_profile_merge(self.handle, other.handle))

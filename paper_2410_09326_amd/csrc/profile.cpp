@@ -183,6 +183,47 @@ int32_t qops_profile_dump(const qops_profile* pr, const char* path)
     return QOPS_OK;
 }
 
+int32_t qops_profile_trace(const qops_profile* pr, const char* path)
+{
+    if (!pr || !path) return set_error(QOPS_INVALID_ARG, "null argument");
+    FILE* f = std::fopen(path, "w");
+    if (!f) return set_error(QOPS_INVALID_ARG, std::string("cannot open ") + path);
+    static const char* kinds[] = {"register tile", "LDS tile", "whole state in LDS", "sweep", "bit swap"};
+    const int nk = (int)(sizeof(kinds) / sizeof(kinds[0]));
+    std::fprintf(f, "{\"displayTimeUnit\": \"ms\", \"traceEvents\": [\n");
+    std::fprintf(f, "{\"name\": \"process_name\", \"ph\": \"M\", \"pid\": 1, \"args\": {\"name\": "
+                    "\"qops %d qubits %s\"}},\n",
+                 pr->n, pr->prec == QOPS_C64 ? "complex64" : "complex128");
+    std::fprintf(f, "{\"name\": \"thread_name\", \"ph\": \"M\", \"pid\": 1, \"tid\": 1, \"args\": {\"name\": "
+                    "\"passes\"}}");
+    for (const qops_pass_record& r : pr->recs) {
+        const char* kind = r.type >= 0 && r.type < nk ? kinds[r.type] : "pass";
+        const double gbs = r.seconds > 0 ? r.bytes_alg / r.seconds / 1e9 : 0.0;
+        std::fprintf(f,
+                     ",\n{\"name\": \"%s\", \"cat\": \"pass\", \"ph\": \"X\", \"pid\": 1, \"tid\": 1, "
+                     "\"ts\": %.3f, \"dur\": %.3f, \"args\": {\"pass\": %d, \"tile_bits\": %d, \"ops\": %d, "
+                     "\"gates\": %d, \"mfma_ops\": %d, \"max_k\": %d, \"remaps\": %d, \"bytes\": %.6g, "
+                     "\"flops\": %.6g, \"GB_per_s\": %.1f, \"phys_mask\": %llu}}",
+                     kind, r.t_begin * 1e6, r.seconds * 1e6, r.pass, r.tile_bits, r.n_ops, r.n_gates, r.n_mfma,
+                     r.max_k, r.n_remaps, r.bytes_alg, r.flops, gbs, (unsigned long long)r.phys_mask);
+    }
+    // gates per logical qubit (all kinds), as counters at t = 0
+    const int n = pr->n;
+    if (!pr->lcount.empty())
+        for (int q = 0; q < n; ++q) {
+            long long c = 0;
+            for (int k = 0; k < QOPS_NUM_KINDS; ++k) c += pr->lcount[(size_t)k * n + q];
+            std::fprintf(f, ",\n{\"name\": \"gates on q%d\", \"ph\": \"C\", \"pid\": 1, \"ts\": 0, "
+                            "\"args\": {\"gates\": %lld}}",
+                         q, c);
+        }
+    std::fprintf(f, "\n]}\n");
+    const bool ok = std::ferror(f) == 0;
+    std::fclose(f);
+    if (!ok) return set_error(QOPS_INVALID_ARG, std::string("write failed: ") + path);
+    return QOPS_OK;
+}
+
 int32_t qops_profile_merge(qops_profile* dst, const qops_profile* src)
 {
     if (!dst || !src) return set_error(QOPS_INVALID_ARG, "null argument");

@@ -201,3 +201,26 @@ def test_block_fusion_counts():
     # still joins the block
     ops4 = q.Plan(n, gates + [("cx", (4, 7)), ("h", (2,))], max_fuse_k=3).ops()
     assert len(ops4) == 2
+
+
+def test_profile_trace_export(tmp_path):
+    """A stored profile exports as a Chrome trace-event file: one complete
+    event per pass (start, duration, achieved GB/s) on the passes track."""
+    import json
+    import os
+    models = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2410_09326_amd",
+                          "models")
+    prof = q.Profile.load(os.path.join(models, "corpus_profile.bin"))
+    recs = prof.records()
+    path = str(tmp_path / "trace.json")
+    prof.trace(path)
+    with open(path) as fh:
+        d = json.load(fh)
+    ev = d["traceEvents"]
+    xs = [e for e in ev if e["ph"] == "X"]
+    assert len(xs) == len(recs)
+    for e, r in zip(xs[:200], recs[:200]):
+        assert e["dur"] == pytest.approx(r["seconds"] * 1e6, rel=1e-5, abs=1e-3)
+        assert e["args"]["pass"] == r["pass"] and e["args"]["ops"] == r["n_ops"]
+        assert e["args"]["GB_per_s"] == pytest.approx(r["bytes_alg"] / r["seconds"] / 1e9, rel=1e-3, abs=0.1)
+    assert any(e["ph"] == "M" for e in ev)
