@@ -61,6 +61,7 @@ def lib():
         L.orc_norm.restype = ctypes.c_double
         L.orc_probabilities.argtypes = [ctypes.c_int, dp, ctypes.c_int, ip, dp]
         L.orc_expect_z.argtypes = [ctypes.c_int, dp, dp]
+        L.orc_expect_zz.argtypes = [ctypes.c_int, dp, ip, ctypes.c_int, dp]
         _lib = L
     return _lib
 
@@ -195,6 +196,25 @@ def expect_z(psi: np.ndarray) -> np.ndarray:
     out = np.zeros(n, dtype=np.float64)
     lib().orc_expect_z(n, _dp(psi.view(np.float64)), _dp(out))
     return out
+
+
+def expect_zz(psi: np.ndarray, pairs) -> np.ndarray:
+    """<Z_a Z_b> for every (a, b) in pairs (Sec. IV-E: the correlators of a
+    diagonal cost Hamiltonian)."""
+    psi = np.ascontiguousarray(psi, dtype=np.complex128)
+    n = int(round(np.log2(psi.size)))
+    pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+    out = np.zeros(len(pr), dtype=np.float64)
+    lib().orc_expect_zz(n, _dp(psi.view(np.float64)), pr.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(pr),
+                        _dp(out))
+    return out
+
+
+def maxcut_expectation(zz: np.ndarray, weights) -> float:
+    """<C> of the Max-Cut cost C = sum_e w_e (1 - Z_a Z_b) / 2 from its
+    correlators."""
+    w = np.asarray(weights, dtype=np.float64)
+    return float(np.sum(w * (1.0 - np.asarray(zz, dtype=np.float64))) / 2.0)
 
 
 def expected_layout(n: int, gates, virtual_swaps: bool = True) -> np.ndarray:

@@ -251,6 +251,23 @@ void orc_probabilities(int n, const double* psi, int m, const int* q, double* ou
     }
 }
 
+/* <Z_a Z_b> = sum_x |psi_x|^2 (-1)^(b_a(x) + b_b(x)) for each pair (a, b) =
+ * (pairs[2i], pairs[2i+1]); the two-qubit correlators a diagonal cost
+ * Hamiltonian such as Max-Cut's is built from (repeated QAOA runs, paper
+ * Sec. IV-E).  Plain sequential sum over x. */
+void orc_expect_zz(int n, const double* psi, const int* pairs, int npairs, double* out)
+{
+    for (int i = 0; i < npairs; ++i) out[i] = 0.0;
+    const uint64_t N = 1ull << n;
+    for (uint64_t x = 0; x < N; ++x) {
+        double p = psi[2 * x] * psi[2 * x] + psi[2 * x + 1] * psi[2 * x + 1];
+        for (int i = 0; i < npairs; ++i) {
+            const uint64_t s = ((x >> pairs[2 * i]) ^ (x >> pairs[2 * i + 1])) & 1ull;
+            out[i] += s ? -p : p;
+        }
+    }
+}
+
 /* <Z_q> = sum_x |psi_x|^2 (1 - 2 b_q(x)) for every qubit q, in index order. */
 void orc_expect_z(int n, const double* psi, double* out)
 {

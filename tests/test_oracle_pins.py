@@ -303,3 +303,67 @@ def test_adam_reduces_loss():
         _, g = mlp.backward(p, X, t)
         mlp.adam_step(p, g, m, v, s, 1e-3)
     assert mlp.loss(p, X, t) < 0.1 * l0
+
+
+# ---------------------------------------------------------------------------
+# Two-qubit correlators and the Max-Cut cost (repeated QAOA runs, Sec. IV-E)
+# ---------------------------------------------------------------------------
+
+def test_expect_zz_closed_forms():
+    n = 6
+    # GHZ: every pair perfectly correlated
+    pairs = [(a, b) for a in range(n) for b in range(a + 1, n)]
+    zz = orc.expect_zz(orc.run_circuit(W.ghz(n)), pairs)
+    assert np.allclose(zz, 1.0, atol=1e-14)
+    # product state RY(t_q)|0>: <Z_a Z_b> = cos t_a cos t_b; <Z_a Z_a> = 1
+    th = np.linspace(0.3, 2.9, n)
+    c = W.Circuit(n, [W.Gate("ry", (q,), params=(float(th[q]),)) for q in range(n)])
+    zz = orc.expect_zz(orc.run_circuit(c), pairs + [(2, 2)])
+    ref = [np.cos(th[a]) * np.cos(th[b]) for a, b in pairs] + [1.0]
+    assert np.max(np.abs(zz - ref)) < 1e-14
+
+
+def test_maxcut_of_basis_states_is_the_cut_weight():
+    edges, w = W.regular_graph(3, 8, 3)
+    for x in (0, 0b10110010, 0b11111111, 0b01010101):
+        zz = orc.expect_zz(orc.basis_state(8, x), edges)
+        cut = sum(wi for (a, b), wi in zip(edges, w) if ((x >> a) ^ (x >> b)) & 1)
+        assert abs(orc.maxcut_expectation(zz, w) - cut) < 1e-13
+
+
+def test_qaoa_single_edge_closed_form():
+    # one edge, p = 1: <C> = 1/2 + sin(4 beta) sin(gamma) / 2
+    for gm, bt in ((0.3, 0.7), (1.1, 0.2), (2.0, 1.3)):
+        c = W.qaoa_maxcut(2, [(0, 1)], [1.0], [gm], [bt])
+        zz = orc.expect_zz(orc.run_circuit(c), [(0, 1)])
+        assert abs(orc.maxcut_expectation(zz, [1.0]) - (0.5 + 0.5 * np.sin(4 * bt) * np.sin(gm))) < 1e-13
+
+
+def test_qaoa_matches_dense_matrix_exponentials():
+    """n = 6, p = 2 on a weighted graph against numpy matrix exponentials of
+    the cost and mixer Hamiltonians built from Kronecker products."""
+    from scipy.linalg import expm
+    n = 6
+    edges, w = W.regular_graph(1, n, 3)
+    gms, bts = [0.4, 0.9], [0.6, 0.25]
+    X = np.array([[0, 1], [1, 0]], dtype=complex)
+    Z = np.diag([1.0, -1.0]).astype(complex)
+
+    def on(op, q):   # qubit q = bit q: the Kronecker factor order is reversed
+        mats = [np.eye(2, dtype=complex)] * n
+        mats = list(mats)
+        mats[n - 1 - q] = op
+        out = mats[0]
+        for m in mats[1:]:
+            out = np.kron(out, m)
+        return out
+    C = sum(wi * (np.eye(2 ** n) - on(Z, a) @ on(Z, b)) / 2 for (a, b), wi in zip(edges, w))
+    B = sum(on(X, q) for q in range(n))
+    psi = np.ones(2 ** n, dtype=complex) / np.sqrt(2 ** n)
+    for gm, bt in zip(gms, bts):
+        psi = expm(-1j * bt * B) @ (expm(-1j * gm * C) @ psi)
+    ref = float(np.real(np.conj(psi) @ C @ psi))
+    got_psi = orc.run_circuit(W.qaoa_maxcut(n, edges, w, gms, bts))
+    # equal up to a global phase; the expectation is phase free
+    assert abs(abs(np.vdot(psi, got_psi)) - 1) < 1e-12
+    assert abs(orc.maxcut_expectation(orc.expect_zz(got_psi, edges), w) - ref) < 1e-12

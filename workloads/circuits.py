@@ -289,6 +289,37 @@ def param_sweep_batch(seed: int = 5, count: int = 512, nmin: int = 10, nmax: int
     return out
 
 
+def regular_graph(seed: int, n: int, degree: int = 3) -> Tuple[List[Tuple[int, int]], np.ndarray]:
+    """A seeded random degree-regular simple graph on n vertices (pairing
+    model: shuffle the n*degree half-edges, pair them in order, redraw until
+    there is no self-loop or double edge) and edge weights U[0.5, 1.5)."""
+    rng = rng_for(seed)
+    assert (n * degree) % 2 == 0 and degree < n
+    while True:
+        stubs = np.repeat(np.arange(n), degree)
+        rng.shuffle(stubs)
+        pairs = stubs.reshape(-1, 2)
+        edges = {(int(min(a, b)), int(max(a, b))) for a, b in pairs}
+        if len(edges) == len(pairs) and all(a != b for a, b in edges):
+            break
+    e = sorted(edges)
+    return e, rng.uniform(0.5, 1.5, len(e))
+
+
+def qaoa_maxcut(n: int, edges, weights, gammas: Sequence[float], betas: Sequence[float]) -> Circuit:
+    """QAOA for weighted Max-Cut, C = sum_e w_e (1 - Z_a Z_b) / 2: H on every
+    qubit, then per layer l the cost unitary exp(-i gamma_l C) (up to a global
+    phase: RZZ(-gamma_l w_e) on every edge, RZZ(t) = exp(-i t/2 Z Z)) and the
+    mixer exp(-i beta_l sum X) (RX(2 beta_l) on every qubit)."""
+    g: List[Gate] = [Gate("h", (q,)) for q in range(n)]
+    for gm, bt in zip(gammas, betas):
+        for (a, b), w in zip(edges, weights):
+            g.append(Gate("rzz", (int(a), int(b)), params=(float(-gm * w),)))
+        for q in range(n):
+            g.append(Gate("rx", (q,), params=(float(2.0 * bt),)))
+    return Circuit(n, g, name=f"qaoa{n}_p{len(gammas)}")
+
+
 def mlp_init(seed: int, sizes: Sequence[int] = (64, 128, 128, 1)) -> np.ndarray:
     """Seeded He-uniform initial weights of the cost-model perceptron, flat
     float64 in the order W1, b1, W2, b2, W3, b3 (W_i is out x in, row-major;
