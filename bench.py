@@ -199,6 +199,49 @@ def batch_sweep(reps: int):
             "max_abs_vs_c128_sample": err}
 
 
+def qaoa_sweep(n: int = 28, layers: int = 3, evals: int = 16):
+    """Repeated QAOA Max-Cut runs on a seeded 3-regular weighted graph: the
+    plan is built once and re-bound to each new angle set; one evaluation =
+    re-bind + |0..0> + the circuit + the edge correlators <Z_a Z_b>, from
+    which <C> = sum_e w_e (1 - <Z_a Z_b>) / 2 follows."""
+    import numpy as np
+    import torch
+    import paper_2410_09326_amd as q
+    from workloads import circuits as W
+    edges, w = W.regular_graph(11, n, 3)
+    rng = np.random.default_rng(5)
+    sets = [(rng.uniform(0, np.pi, layers), rng.uniform(0, np.pi / 2, layers)) for _ in range(evals + 1)]
+    c0 = W.qaoa_maxcut(n, edges, w, *sets[0])
+    t0 = time.perf_counter()
+    plan = q.Plan(n, c0.gates, precision=q.C64)
+    plan_s = time.perf_counter() - t0
+    sim = q.Simulator(n, q.C64)
+    sim.init_basis(0)
+    sim.run(plan)
+    sim.expect_zz(edges)
+    costs, t_upd = [], 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for gm, bt in sets[1:]:
+        c = W.qaoa_maxcut(n, edges, w, gm, bt)
+        ga = q.GateArray(c.gates)
+        u0 = time.perf_counter()
+        plan.update(ga)
+        t_upd += time.perf_counter() - u0
+        sim.init_basis(0)
+        sim.run(plan)
+        zz = sim.expect_zz(edges)
+        costs.append(float(np.sum(w * (1.0 - zz)) / 2.0))
+    el = time.perf_counter() - t0
+    sim.close()
+    return {"workload": f"QAOA Max-Cut, {n} qubits, p={layers}, seeded 3-regular weighted graph "
+                        f"({len(edges)} edges), complex64, {evals} angle sets on one re-bound plan",
+            "evals_per_s": round(evals / el, 2), "ms_per_eval": round(el / evals * 1e3, 3),
+            "rebind_ms_per_eval": round(t_upd / evals * 1e3, 3), "plan_ms": round(plan_s * 1e3, 3),
+            "passes": plan.stats()["n_passes"], "best_cost": round(max(costs), 6),
+            "total_weight": round(float(np.sum(w)), 6)}
+
+
 def main() -> None:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,6 +253,7 @@ def main() -> None:
     ap.add_argument("--no-learned-eval", action="store_true")
     ap.add_argument("--eval-circuits", type=int, default=10)
     ap.add_argument("--no-batch-eval", action="store_true")
+    ap.add_argument("--no-qaoa-eval", action="store_true")
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--dump-passes", default="", help="write the last step's pass records (JSON) here")
     ap.add_argument("--trace", default="", help="write the last step's profile as a Chrome trace here")
@@ -333,6 +377,8 @@ def main() -> None:
         out["learned_vs_plain"] = learned_vs_plain(args.eval_circuits)
     if not args.no_batch_eval:
         out["batch_sweep"] = batch_sweep(args.batch_reps)
+    if not args.no_qaoa_eval:
+        out["qaoa_sweep"] = qaoa_sweep()
     if not args.no_cpu_baseline:
         cb = cpu_baseline(circ, args.cpu_seconds)
         out["cpu_baseline"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in cb.items()

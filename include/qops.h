@@ -223,8 +223,11 @@ int32_t qops_plan_pass_info(const qops_plan* p, size_t i, qops_pass_info* info);
  * must equal the plan's; otherwise QOPS_BAD_STATE).  Asynchronous. */
 int32_t qops_run_plan(qops_sim* h, const qops_plan* p);
 /* Re-binds the angles / dense matrices of a plan to a new gate list with the
- * same structure (same kinds and qubits), re-composing fused blocks in FP64
- * without re-planning.  For repeated runs with new parameters. */
+ * same structure (same kinds, qubits and controls): the planner runs again on
+ * the new parameters with the plan's options, so fused blocks are re-composed
+ * in FP64 and the pass structure is kept; the device buffers of the plan are
+ * reused.  For repeated runs with new parameters (QAOA angle sweeps).
+ * QOPS_BAD_STATE if the structure differs. */
 int32_t qops_plan_update(qops_plan* p, const qops_gate* gates, size_t n_gates);
 
 /* Plans (opts may be null = defaults) and runs a gate list.  Asynchronous. */
@@ -400,6 +403,14 @@ int32_t qops_probabilities(qops_sim* h, const int32_t* qubits, int32_t m, double
 /* <Z_q> = sum_x |psi_x|^2 (1 - 2 b_q(x)) for every logical qubit (n
  * doubles).  FP64, deterministic.  Blocking. */
 int32_t qops_expect_z(qops_sim* h, double* out);
+/* <Z_a Z_b> = sum_x |psi_x|^2 (-1)^(b_a(x) + b_b(x)) for each pair of logical
+ * qubits (a, b) = (pairs[2i], pairs[2i+1]), i < npairs: the correlators a
+ * diagonal cost Hamiltonian such as weighted Max-Cut's,
+ * C = sum_e w_e (1 - Z_a Z_b) / 2, is evaluated from in repeated QAOA runs
+ * (paper Sec. IV-E).  out holds npairs doubles.  FP64, deterministic; one
+ * read of the state per eight pairs.  QOPS_QUBIT_RANGE for a qubit outside
+ * [0, n).  Blocking. */
+int32_t qops_expect_zz(qops_sim* h, const int32_t* pairs, int32_t npairs, double* out);
 /* Waits for all work enqueued on the handle's stream. */
 int32_t qops_synchronize(qops_sim* h);
 

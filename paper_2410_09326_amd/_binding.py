@@ -153,6 +153,7 @@ SIGNATURES = {
     "qops_norm": (_I32, [_VP, _DP]),
     "qops_probabilities": (_I32, [_VP, _IP, _I32, _DP]),
     "qops_expect_z": (_I32, [_VP, _DP]),
+    "qops_expect_zz": (_I32, [_VP, _IP, _I32, _DP]),
     "qops_synchronize": (_I32, [_VP]),
 }
 
@@ -656,6 +657,13 @@ class Simulator:
     def expect_z(self) -> np.ndarray:
         out = np.empty(self.n, dtype=np.float64)
         check(lib().qops_expect_z(self.handle, out.ctypes.data_as(_DP)))
+        return out
+
+    def expect_zz(self, pairs) -> np.ndarray:
+        """<Z_a Z_b> for every pair (a, b) of logical qubits."""
+        pr = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+        out = np.zeros(len(pr), dtype=np.float64)
+        check(lib().qops_expect_zz(self.handle, pr.ctypes.data_as(_IP), len(pr), out.ctypes.data_as(_DP)))
         return out
 
     def synchronize(self) -> None:

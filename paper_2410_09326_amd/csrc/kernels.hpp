@@ -59,6 +59,12 @@ hipError_t launch_gather_logical(int prec, const void* state, int n, const int* 
 // Batched executor kernels.
 #define QOPS_BATCH_SMALL_MAX 13
 #define QOPS_BATCH_REC 32   // doubles per <Z> partial record (n + 1 <= 27)
+// <Z_a Z_b> for physical bit pairs (pa[i], pb[i]): partials in `part`
+// (zz_scratch_doubles(n) doubles), results in d_out[0..npairs).
+size_t zz_scratch_doubles(int n);
+hipError_t launch_expect_zz(int prec, const void* state, int n, const int32_t* pa, const int32_t* pb, int npairs,
+                            double* part, double* d_out, hipStream_t s);
+
 hipError_t launch_batch_small(int prec, const int32_t* ids, int count, const BatchCirc* circs, const DevOp* ops,
                               const void* coef, double* out, int lds_bytes, hipStream_t s);
 hipError_t launch_batch_pass(int prec, const BatchItem* items, int nitems, const BatchCirc* circs, const PassHdr* hdrs,

@@ -174,6 +174,36 @@ PlanParams params_from(const qops_plan_opts* o, int n, int prec)
 
 }  // namespace qops
 
+namespace qops {
+
+int32_t expect_zz(qops_sim* h, const int32_t* pairs, int32_t npairs, double* out)
+{
+    if (!h || (npairs > 0 && (!pairs || !out))) return set_error(QOPS_INVALID_ARG, "null argument");
+    if (npairs < 0) return set_error(QOPS_INVALID_ARG, "npairs < 0");
+    if (npairs == 0) return QOPS_OK;
+    std::vector<int32_t> pa((size_t)npairs);
+    std::vector<int32_t> pb((size_t)npairs);
+    for (int i = 0; i < npairs; ++i) {
+        const int a = pairs[2 * i];
+        const int b = pairs[2 * i + 1];
+        if (a < 0 || a >= h->n || b < 0 || b >= h->n) return set_error(QOPS_QUBIT_RANGE, "qubit out of range");
+        pa[i] = h->l2p[a];
+        pb[i] = h->l2p[b];
+    }
+    const size_t part = zz_scratch_doubles(h->n);
+    int32_t rc = ensure_scratch(h, part + (size_t)npairs);
+    if (rc) return rc;
+    hipError_t e = launch_expect_zz(h->prec, h->state, h->n, pa.data(), pb.data(), npairs, h->scratch,
+                                    h->scratch + part, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, h->scratch + part, (size_t)npairs * sizeof(double), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(e, "expect_zz");
+    return QOPS_OK;
+}
+
+}  // namespace qops
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -537,6 +567,11 @@ int32_t qops_expect_z(qops_sim* h, double* out)
         for (int q = 0; q < h->n; ++q) out[q] = v[0] - 2.0 * v[1 + h->l2p[q]];
         return QOPS_OK;
     });
+}
+
+int32_t qops_expect_zz(qops_sim* h, const int32_t* pairs, int32_t npairs, double* out)
+{
+    QOPS_GUARD(return qops::expect_zz(h, pairs, npairs, out));
 }
 
 int32_t qops_probabilities(qops_sim* h, const int32_t* qubits, int32_t m, double* out)
