@@ -157,6 +157,12 @@ typedef struct qops_plan_opts {
                               modes decide this themselves                    */
     const qops_profile* profile;  /* PROFILED / LEARNED pricing input         */
     const qops_model* model;      /* LEARNED pricing input                    */
+    int32_t fold_rotations;        /* rotation folding (paper Sec. III-D):
+                                      diagonal phases on equal parities of the
+                                      path variables merge across CNOT / X /
+                                      SWAP; 1 = on, -1 = off, 0 = the paper's
+                                      rule (on when T gates exceed 10% of the
+                                      gates).  Exact, global phase included.  */
 } qops_plan_opts;
 
 /* Fills opts with the defaults listed above. */
@@ -182,6 +188,7 @@ typedef struct qops_plan_stats {
     double bytes_alg;          /* algorithmic HBM bytes of all passes         */
     double predicted_s;        /* cost-model prediction (0 if not priced)     */
     double plan_seconds;       /* host time spent building the plan           */
+    int32_t n_folded;          /* phase gates removed by rotation folding     */
 } qops_plan_stats;
 int32_t qops_plan_stats_get(const qops_plan* p, qops_plan_stats* out);
 /* The layout (l2p) the plan leaves behind. */

@@ -43,14 +43,16 @@ class Gate(ctypes.Structure):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("swap_mode", ctypes.c_int32), ("tile_upper", ctypes.c_int32),
                 ("max_fuse_k", ctypes.c_int32), ("use_mfma", ctypes.c_int32), ("check_unitary", ctypes.c_int32),
-                ("remap", ctypes.c_int32), ("profile", ctypes.c_void_p), ("model", ctypes.c_void_p)]
+                ("remap", ctypes.c_int32), ("profile", ctypes.c_void_p), ("model", ctypes.c_void_p),
+                ("fold_rotations", ctypes.c_int32)]
 
 
 class PlanStats(ctypes.Structure):
     _fields_ = [("n_passes", ctypes.c_int32), ("n_tile_passes", ctypes.c_int32),
                 ("n_permute_passes", ctypes.c_int32), ("n_ops", ctypes.c_int32), ("n_gates_in", ctypes.c_int32),
                 ("n_virtual_swaps", ctypes.c_int32), ("tile_upper", ctypes.c_int32), ("max_fuse_k", ctypes.c_int32),
-                ("bytes_alg", ctypes.c_double), ("predicted_s", ctypes.c_double), ("plan_seconds", ctypes.c_double)]
+                ("bytes_alg", ctypes.c_double), ("predicted_s", ctypes.c_double), ("plan_seconds", ctypes.c_double),
+                ("n_folded", ctypes.c_int32)]
 
 
 class PassRecord(ctypes.Structure):
@@ -241,13 +243,15 @@ class GateArray:
 
 
 def plan_opts(mode: int = PLAN_FUSED, swap_mode: int = SWAP_VIRTUAL, tile_upper: int = 0, max_fuse_k: int = 0,
-              use_mfma: int = 1, check_unitary: int = 0, remap: int = 0, profile=None, model=None) -> PlanOpts:
+              use_mfma: int = 1, check_unitary: int = 0, remap: int = 0, profile=None, model=None,
+              fold_rotations: int = 0) -> PlanOpts:
     o = PlanOpts()
     check(lib().qops_plan_opts_default(ctypes.byref(o)))
     o.mode, o.swap_mode, o.tile_upper = mode, swap_mode, tile_upper
     o.max_fuse_k, o.use_mfma, o.check_unitary, o.remap = max_fuse_k, use_mfma, check_unitary, remap
     o.profile = profile.handle if profile is not None else None
     o.model = model.handle if model is not None else None
+    o.fold_rotations = fold_rotations
     return o
 
 

@@ -41,7 +41,7 @@ int gate_arity(int kind)
     return -1;
 }
 
-static bool diag_kind(int kind)
+bool diag_kind(int kind)
 {
     switch (kind) {
     case QOPS_Z: case QOPS_S: case QOPS_SDG: case QOPS_T: case QOPS_TDG: case QOPS_RZ: case QOPS_P:
@@ -1182,7 +1182,19 @@ Err build_plan(int n, int prec, const int32_t* l2p_in, const qops_gate* g, size_
             p2l[l2p[other]] = other;
         }
     }
-    e = lower(n, p.gates.data(), ng, par.swap_mode, l2p, lowered, p.n_virtual_swaps);
+    // rotation folding (paper Sec. III-D): on request, or by the paper's rule
+    // (T gates above 10% of the circuit) unless switched off
+    const qops_gate* lg = p.gates.data();
+    size_t lng = ng;
+    std::vector<qops_gate> folded;
+    p.n_folded = 0;
+    if (par.mode != QOPS_PLAN_GATEWISE &&
+        (par.fold > 0 || (par.fold == 0 && fold_rule_fires(p.gates.data(), ng)))) {
+        fold_rotations(n, p.gates.data(), ng, folded, p.n_folded);
+        lg = folded.data();
+        lng = folded.size();
+    }
+    e = lower(n, lg, lng, par.swap_mode, l2p, lowered, p.n_virtual_swaps);
     if (!e.ok()) return e;
     p.l2p_out = l2p;
     if (par.mode == QOPS_PLAN_GATEWISE) {

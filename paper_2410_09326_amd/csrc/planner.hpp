@@ -54,6 +54,7 @@ struct PlanParams {
     int check_unitary = 0;
     int remap = 0;             // move the most-targeted qubits into physical bits 0..5 first
     int force_lds = 0;         // every tile pass is an LDS pass (batched executor)
+    int fold = 0;              // rotation folding: 1 on, -1 off, 0 by the T-gate rule
 };
 
 struct Plan {
@@ -68,6 +69,7 @@ struct Plan {
     std::vector<DevOp> dops;
     std::vector<double> coef;          // FP64 image; cast to the state precision at upload
     int n_virtual_swaps = 0;
+    int n_folded = 0;                  // phase gates removed by rotation folding
     double plan_seconds = 0;
     double predicted_s = 0;
     // device copies (uploaded lazily by the runtime)
@@ -85,6 +87,11 @@ struct Err {
 };
 
 int gate_arity(int kind);
+bool diag_kind(int kind);
+// Rotation folding over phase polynomials; `removed` = input phase gates
+// minus the phase gates of the result.
+bool fold_rule_fires(const qops_gate* g, size_t ng);
+void fold_rotations(int n, const qops_gate* in, size_t ng, std::vector<qops_gate>& out, int& removed);
 // The gate's matrix (ordered targets, little-endian bit order), FP64.
 Err gate_matrix(const qops_gate& g, std::vector<cd>& out);
 Err validate_gates(int n, const qops_gate* g, size_t ng, bool check_unitary);

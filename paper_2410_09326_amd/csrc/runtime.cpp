@@ -165,6 +165,7 @@ PlanParams params_from(const qops_plan_opts* o, int n, int prec)
         par.L_lds = std::min(6 + o->tile_upper, prec == QOPS_C64 ? 13 : 12);
     }
     par.max_fuse_k = o->max_fuse_k > 0 ? o->max_fuse_k : 1;
+    par.fold = o->fold_rotations > 0 ? 1 : (o->fold_rotations < 0 ? -1 : 0);
     par.remap = o->remap;
     par.use_mfma = o->use_mfma;
     par.check_unitary = o->check_unitary;
@@ -347,6 +348,7 @@ int32_t qops_plan_stats_get(const qops_plan* p, qops_plan_stats* s)
     s->n_virtual_swaps = q.n_virtual_swaps;
     s->tile_upper = q.par.R + q.par.W;
     s->max_fuse_k = q.par.max_fuse_k;
+    s->n_folded = q.n_folded;
     s->predicted_s = q.predicted_s;
     s->plan_seconds = q.plan_seconds;
     return QOPS_OK;

@@ -169,3 +169,14 @@ def test_fused_blocks(q, prec, kmax):
     for c in (W.qft_then_layers(1, n=16, layers=4), W.random_mix_layers(9, 17, 6)):
         got, l2p = run_gpu(q, c, prec, max_fuse_k=kmax)
         check_state(got, orc.run_circuit(c), prec, f"{c.name} kmax={kmax}")
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_rotation_folding(q, prec):
+    """Clifford+T circuits with rotation folding on, off and by the T-gate
+    rule agree with the oracle (exact folding: no global-phase freedom)."""
+    for c in (W.clifford_t(1, 15, 600), W.clifford_t(3, 19, 900, t_frac=0.5)):
+        ref = orc.run_circuit(c)
+        for fold in (1, -1, 0):
+            got, _ = run_gpu(q, c, prec, fold_rotations=fold)
+            check_state(got, ref, prec, f"{c.name} fold={fold}")

@@ -120,7 +120,7 @@ def test_single_qubit_merging_and_diag_fusion_counts():
     for _ in range(5):
         gates += [("h", (3,)), ("t", (3,)), ("rz", (3,), (0.3,)), ("s", (9,))]
     gates += [("cz", (0, 1)), ("cz", (2, 3)), ("cp", (4, 5), (0.2,))]
-    plan = q.Plan(n, gates)
+    plan = q.Plan(n, gates, fold_rotations=-1)
     ops = plan.ops()
     # all one-qubit gates on qubit 3 collapse to one 2x2; the five S on 9 to one
     # controlled phase; controlled phases on different bits stay separate
@@ -224,3 +224,43 @@ def test_profile_trace_export(tmp_path):
         assert e["args"]["pass"] == r["pass"] and e["args"]["ops"] == r["n_ops"]
         assert e["args"]["GB_per_s"] == pytest.approx(r["bytes_alg"] / r["seconds"] / 1e9, rel=1e-3, abs=0.1)
     assert any(e["ph"] == "M" for e in ev)
+
+
+FOLD_CASES = CASES + [
+    ("clifft10", lambda: W.clifford_t(1, 10, 300)),
+    ("clifft13", lambda: W.clifford_t(2, 13, 500, t_frac=0.5)),
+    ("qaoa10", lambda: W.qaoa_maxcut(10, *W.regular_graph(2, 10, 3), [0.4, 1.1], [0.3, 0.8])),
+]
+
+
+@pytest.mark.parametrize("name,make", FOLD_CASES)
+@pytest.mark.parametrize("swap_mode", [q.SWAP_VIRTUAL, q.SWAP_PHYSICAL])
+def test_rotation_folding_is_exact(name, make, swap_mode):
+    """Folded plans reproduce the circuit exactly, global phase included."""
+    c = make()
+    plan = q.Plan(c.n, c.gates, precision=q.C128, fold_rotations=1, swap_mode=swap_mode)
+    got = physical_replay(c.n, plan, c.x0)
+    assert np.max(np.abs(got - orc.run_circuit(c))) <= 1e-12
+    assert np.array_equal(plan.final_layout(),
+                          orc.expected_layout(c.n, c.gates, virtual_swaps=(swap_mode == q.SWAP_VIRTUAL)))
+
+
+def test_rotation_folding_merges_equal_parities():
+    n = 8
+    # T and T-dagger on the same parity a xor b (behind CNOTs) cancel
+    cancel = [("cx", (2, 5)), ("t", (5,)), ("cx", (2, 5)), ("h", (7,)), ("cx", (2, 5)), ("tdg", (5,)), ("cx", (2, 5))]
+    st = q.Plan(n, cancel, fold_rotations=1).stats()
+    assert st["n_folded"] == 2
+    # T on wire 3, a detour through CNOTs, T again on the same parity: one S
+    two = [("t", (3,)), ("cx", (3, 4)), ("cx", (4, 6)), ("cx", (3, 4)), ("cx", (4, 6)), ("t", (3,))]
+    p2 = q.Plan(n, two, fold_rotations=1)
+    assert p2.stats()["n_folded"] == 1
+    # a Hadamard on the wire starts a new parity: nothing merges
+    three = [("t", (3,)), ("h", (3,)), ("t", (3,))]
+    assert q.Plan(n, three, fold_rotations=1).stats()["n_folded"] == 0
+    # the paper's activation rule: folding fires above 10% T gates only
+    lots = W.clifford_t(4, n, 200, t_frac=0.4)
+    few = W.clifford_t(4, n, 200, t_frac=0.02)
+    assert q.Plan(n, lots.gates).stats()["n_folded"] > 0
+    assert q.Plan(n, few.gates).stats()["n_folded"] == 0
+    assert q.Plan(n, lots.gates, fold_rotations=-1).stats()["n_folded"] == 0

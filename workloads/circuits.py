@@ -289,6 +289,25 @@ def param_sweep_batch(seed: int = 5, count: int = 512, nmin: int = 10, nmax: int
     return out
 
 
+def clifford_t(seed: int, n: int, ngates: int, t_frac: float = 0.3) -> Circuit:
+    """Seeded Clifford+T circuit (the gate mix of reversible arithmetic
+    benchmarks): with probability t_frac a T or T-dagger, otherwise H, S, X, Z,
+    CX or CZ, on uniformly drawn qubits."""
+    rng = rng_for(seed)
+    g: List[Gate] = []
+    for _ in range(ngates):
+        if rng.random() < t_frac:
+            g.append(Gate("t" if rng.random() < 0.5 else "tdg", (int(rng.integers(n)),)))
+            continue
+        kind = ("h", "s", "x", "z", "cx", "cx", "cz")[int(rng.integers(7))]
+        if kind in ("cx", "cz"):
+            a, b = rng.choice(n, 2, replace=False)
+            g.append(Gate(kind, (int(a), int(b))))
+        else:
+            g.append(Gate(kind, (int(rng.integers(n)),)))
+    return Circuit(n, g, name=f"clifft{n}_{ngates}_s{seed}")
+
+
 def regular_graph(seed: int, n: int, degree: int = 3) -> Tuple[List[Tuple[int, int]], np.ndarray]:
     """A seeded random degree-regular simple graph on n vertices (pairing
     model: shuffle the n*degree half-edges, pair them in order, redraw until
