@@ -118,7 +118,9 @@ int32_t layout(qops_batch_exec* e)
         e->coef_base[i] = coef_n;
         const int op_base = (int)ops.size();
         for (DevOp d : p.dops) {
-            d.coef += (int32_t)coef_n * (d.b && (d.type == OP_MFMA || d.type == OP_DIAG_LDS) ? 0 : 1);
+            // LDS-tile ops with b = 1 address the pass's staged coefficients
+            const bool staged = d.b && (d.type == OP_MFMA || d.type == OP_DIAG_LDS || d.type == OP_DENSE_LDS);
+            d.coef += staged ? 0 : (int32_t)coef_n;
             ops.push_back(d);
         }
         if (p.n <= e->small_max_n) {

@@ -21,7 +21,7 @@ enum OpType : int32_t {
     OP_CPHASE = 10    // phase coef on amplitudes whose masked bits are all 1   b = 1: phase is -1
 };
 // OP_1Q_REG / OP_1Q_LANE: b = 1 marks an exact X (pure exchange, no arithmetic).
-// OP_MFMA / OP_DIAG_LDS in an LDS tile pass: b = 1 means `coef` is an offset
+// OP_MFMA / OP_DIAG_LDS / OP_DENSE_LDS in an LDS tile pass: b = 1 means `coef` is an offset
 // into the coefficients staged in LDS, b = 0 an offset into global memory.
 
 // Encoded source of one bit of a diagonal's table index (OP_DIAG pos[i]).

@@ -362,7 +362,7 @@ template <int K, typename T>
 struct MfmaShape {
     static constexpr int KS = 1 << (K - 1);    // k-steps of 4 real rows
     static constexpr int RB = 1 << (K - 3);    // row blocks of 16 real rows
-    static constexpr int RW = sizeof(T) == 4 ? (K <= 5 ? 1 : 4) : (K <= 4 ? 1 : (K == 5 ? 2 : 4));
+    static constexpr int RW = K <= 4 ? 1 : (K == 5 ? 2 : 4);
     static constexpr int CW = 4 / RW;          // column groups
     static constexpr int RPW = RB / RW;        // row blocks per wave
     // column blocks in flight (one barrier per chunk if RW > 1): eight
@@ -869,9 +869,9 @@ template <typename T> constexpr int kLdsEpt = sizeof(T) == 4 ? 32 : 16;
 // over tiles; while the operations of tile t run on its LDS copy, the loads
 // of the next tile are already in flight into registers.  Tile element
 // e = 256 u + tid has physical bits 0..5 = e & 63 and bit 6+j = up_phys[j].
-// HK > 0: the pass's one HK-qubit matrix-core block (op hp->hoist) keeps its
-// A fragments in registers for every tile of the work-group, and the other
-// matrix-core blocks of the pass have at most 4 qubits.
+// HK > 0: the pass's widest matrix-core block (HK qubits, op hp->hoist) keeps
+// its A fragments in registers for every tile of the work-group; the other
+// matrix-core blocks of the pass have at most 5 qubits.
 template <typename T, int HK>
 __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1)
 tile_lds_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict__ hp, const DevOp* __restrict__ ops,
@@ -898,8 +898,8 @@ tile_lds_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict__
     const int hoist = HK > 0 ? hp->hoist : -1;
     if constexpr (HK > 0) {
         __syncthreads();   // staged coefficients visible
-        const DevOp hop = prog[hoist];
-        mfma_load_a<HKK, T>(hav, hop.b ? lcoef + hop.coef : coef + hop.coef, lane, wave);
+        const DevOp hop = prog[hoist];   // never staged: read from global memory once
+        mfma_load_a<HKK, T>(hav, coef + hop.coef, lane, wave);
     }
     const uint64_t dep_thr = dep_up((uint32_t)(tid >> 6), hp->up_phys, nup);
     // element 256 u + tid: bit b of u selects physical bit up_phys[2 + b]
@@ -944,13 +944,19 @@ tile_lds_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict__
         for (int i = 0; i < nops; ++i) {
             const DevOp op = prog[i];
             if ((base & op.c_glob) != op.c_glob) continue;
-            const T* cf = op.b ? lcoef + op.coef : coef + op.coef;
+            // complex64 passes hold every coefficient except the hoisted
+            // block's in LDS (the planner guarantees it), so their ops issue
+            // no vector-memory loads and never wait on the next tile's loads
+            // in flight; complex128 ops read from LDS (op.b = 1) or global
+            const T* cf;
+            if constexpr (sizeof(T) == 4) cf = lcoef + op.coef;
+            else cf = op.b ? lcoef + op.coef : coef + op.coef;
             if (op.type == OP_DENSE_LDS) {
-                dense_lds_dispatch<T>(lds, L, op, coef + op.coef, tid, 256);
+                dense_lds_dispatch<T>(lds, L, op, cf, tid, 256);
             } else if (op.type == OP_MFMA) {
                 if constexpr (HK > 0) {
                     if (i == hoist) mfma_core<HKK, T>(lds, L, op, hav, lane, wave);
-                    else mfma_dispatch<T, 4>(lds, L, op, cf, lane, wave);
+                    else mfma_dispatch<T, 5>(lds, L, op, cf, lane, wave);
                 } else {
                     mfma_dispatch<T>(lds, L, op, cf, lane, wave);
                 }
@@ -1668,13 +1674,12 @@ batch_pass_kernel(const BatchItem* __restrict__ items, int nitems, const BatchCi
         for (int j = 0; j < hp->nops; ++j) {
             const DevOp op = prog[j];
             if ((base & op.c_glob) != op.c_glob) continue;
-            const T* cf = op.b ? lcoef + op.coef : coef + op.coef;
-            if (op.type == OP_DENSE_LDS)
-                dense_lds_dispatch<T>(lds, L, op, coef + op.coef, tid, 256);
-            else if (op.type == OP_MFMA)
-                mfma_dispatch<T>(lds, L, op, cf, lane, wave);
-            else if (op.type == OP_DIAG_LDS)
-                diag_lds<T>(lds, L, op, cf, base, tid, 256);
+            const T* cf;
+            if constexpr (sizeof(T) == 4) cf = lcoef + op.coef;
+            else cf = op.b ? lcoef + op.coef : coef + op.coef;
+            if (op.type == OP_DENSE_LDS) dense_lds_dispatch<T>(lds, L, op, cf, tid, 256);
+            else if (op.type == OP_MFMA) mfma_dispatch<T>(lds, L, op, cf, lane, wave);
+            else if (op.type == OP_DIAG_LDS) diag_lds<T>(lds, L, op, cf, base, tid, 256);
             __syncthreads();
         }
         for (uint32_t e = tid; e < N; e += 256) st[base + (e & 63u) + dep_up(e >> 6, hp->up_phys, nup)] = lds[swz(e)];

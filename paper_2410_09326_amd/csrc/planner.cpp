@@ -805,7 +805,21 @@ static size_t staged_bytes(const Plan& p, const LOp& o, int L)
     if (o.kind == LOp::DIAG) return (size_t(2) << o.k) * sz;
     const int k = o.kind == LOp::PSWAP ? 2 : o.k;
     if (o.kind == LOp::DENSE && use_mfma_for(p, k, L)) return (size_t(1) << (2 * (k + 1))) * sz;
-    return 0;
+    return (size_t(2) << (2 * k)) * sz;   // 2^k x 2^k complex for the vector ALU
+}
+
+// The matrix-core block of a complex64 LDS pass whose fragments stay in
+// registers: the first of the widest blocks of 5 or 6 qubits; -1 if none.
+static int hoist_choice(const Plan& p, int op0, int nops)
+{
+    if (p.prec != 0) return -1;
+    int at = -1, best = 4;
+    for (int i = op0; i < op0 + nops; ++i)
+        if (p.dops[i].type == OP_MFMA && p.dops[i].a > best) {
+            best = p.dops[i].a;
+            at = i - op0;
+        }
+    return at;
 }
 
 // LDS of one work-group of the LDS tile kernel: complex64 passes run two
@@ -835,14 +849,21 @@ static void emit_tile_lds(Plan& p, PassPlan& pp)
     const size_t sz = p.prec == 0 ? 4 : 8;
     const size_t tile_bytes = (size_t(1) << pp.L) * 2 * sz;
     size_t room = lds_budget(p.prec) > tile_bytes ? (lds_budget(p.prec) - tile_bytes) / sz : 0;
+    // complex64: the widest matrix-core block of 5 or 6 qubits keeps its
+    // fragments in registers across the pass's tiles (loaded once, before
+    // the tile loop, so it needs no staging); every other op is staged (the
+    // packer keeps them within the LDS budget)
+    h.hoist = hoist_choice(p, h.op0, h.nops);
     h.coef_src = (int)p.coef.size();
     int staged = 0;
     for (int i = h.op0; i < h.op0 + h.nops; ++i) {
         DevOp& d = p.dops[i];
         d.b = 0;
-        if (d.type != OP_MFMA && d.type != OP_DIAG_LDS) continue;
+        if (d.type != OP_MFMA && d.type != OP_DIAG_LDS && d.type != OP_DENSE_LDS) continue;
+        if (i - h.op0 == h.hoist) continue;
         size_t cnt;
         if (d.type == OP_MFMA) cnt = size_t(1) << (2 * (d.a + 1));
+        else if (d.type == OP_DENSE_LDS) cnt = size_t(2) << (2 * d.a);
         else cnt = size_t(2) << d.a;
         if (cnt > room) continue;
         const int off = (int)p.coef.size();
@@ -854,18 +875,6 @@ static void emit_tile_lds(Plan& p, PassPlan& pp)
     }
     h.coef_n = staged;
     h.lds_bytes = (int)(tile_bytes + (size_t)staged * sz);
-    // complex64: a pass with exactly one matrix-core block of 5 or 6 qubits
-    // keeps that block's fragments in registers across its tiles
-    h.hoist = -1;
-    if (p.prec == 0) {
-        int big = 0, at = -1;
-        for (int i = h.op0; i < h.op0 + h.nops; ++i)
-            if (p.dops[i].type == OP_MFMA && p.dops[i].a >= 5) {
-                ++big;
-                at = i - h.op0;
-            }
-        if (big == 1) h.hoist = at;
-    }
     pp.op0 = h.op0;
     pp.nops = h.nops;
     pp.hdr = (int)p.hdrs.size();
@@ -1019,7 +1028,9 @@ static void pack(Plan& p)
     cur.W = W;
     uint64_t S = 0;
     bool dense = false;
-    size_t staged = 0;
+    size_t staged = 0;        // LDS bytes of the staged coefficients
+    int hoist_k = 0;          // complex64: qubits of the block kept in registers
+    size_t hoist_bytes = 0;   //   and its fragment bytes
     auto flush = [&]() {
         if (!cur.lop.empty()) {
             finish_pass(p, cur, S, dense);
@@ -1031,6 +1042,8 @@ static void pack(Plan& p)
         S = 0;
         dense = false;
         staged = 0;
+        hoist_k = 0;
+        hoist_bytes = 0;
     };
     // Greedy packing with look-ahead: a pass opens with the first op not yet
     // placed and then scans forward, taking every op whose bits fit the tile
@@ -1055,17 +1068,44 @@ static void pack(Plan& p)
         const uint64_t need = need_of(o);
         const bool d2 = dense || o.kind == LOp::DENSE || p.par.force_lds;
         const int cap = d2 ? cap_lds : cap_reg;
-        const size_t sb = staged_bytes(p, o, 6 + cap_lds);
-        const size_t tile_bytes = (size_t(1) << (6 + cap_lds)) * (p.prec == 0 ? 8 : 16);
-        // complex128 passes keep all their fragments in LDS (one work-group per
-        // CU); complex64 passes read what does not fit from L2 instead
-        const bool lds_full = p.prec == 1 && d2 && staged + sb + tile_bytes > lds_budget(p.prec) && sb > 0 &&
-                              staged > 0;
+        const int Lt = 6 + cap_lds;
+        const size_t sb = staged_bytes(p, o, Lt);
+        const size_t tile_bytes = (size_t(1) << Lt) * (p.prec == 0 ? 8 : 16);
+        size_t nstaged = staged + sb;
+        int nhoist = hoist_k;
+        bool lds_full;
+        if (p.prec == 0) {
+            // complex64: the widest 5/6-qubit matrix-core block stays in
+            // registers; everything else must fit the LDS budget next to the
+            // tile (two work-groups per CU)
+            const bool big = o.kind == LOp::DENSE && o.k >= 5 && use_mfma_for(p, o.k, Lt);
+            bool ok = true;
+            if (big) {
+                nstaged = staged;
+                if (hoist_k == 0) {
+                    nhoist = o.k;
+                } else if (o.k > hoist_k) {   // the new block takes the registers
+                    nhoist = o.k;
+                    nstaged = staged + hoist_bytes;
+                } else if (o.k == 5) {
+                    nstaged = staged + sb;
+                } else {
+                    ok = false;               // a second 6-qubit block does not fit
+                }
+            }
+            lds_full = !ok || nstaged + tile_bytes > lds_budget(0);
+        } else {
+            // complex128 passes keep all their fragments in LDS (one
+            // work-group per CU)
+            lds_full = d2 && staged + sb + tile_bytes > lds_budget(p.prec) && sb > 0 && staged > 0;
+        }
         if (!cur.lop.empty() && (__builtin_popcountll(S | need) > cap || lds_full)) return false;
         cur.lop.push_back((int)i);
         S |= need;
         dense = d2;
-        staged += sb;
+        if (p.prec == 0 && nhoist != hoist_k) hoist_bytes = staged_bytes(p, o, Lt);
+        hoist_k = nhoist;
+        staged = nstaged;
         return true;
     };
     size_t first = 0;
@@ -1204,6 +1244,16 @@ Err build_plan(int n, int prec, const int32_t* l2p_in, const qops_gate* g, size_
         fuse_blocks(p.lops, std::min(par.max_fuse_k, 6));
     }
     pack(p);
+    // complex64 LDS tile kernels read every coefficient but the hoisted
+    // block's from LDS: each such op must have been staged
+    if (p.prec == 0)
+        for (const PassPlan& pp : p.passes) {
+            if (pp.type != PASS_TILE_LDS) continue;
+            const PassHdr& h = p.hdrs[pp.hdr];
+            for (int i = h.op0; i < h.op0 + h.nops; ++i)
+                if (i - h.op0 != h.hoist && !p.dops[i].b)
+                    return mkerr(QOPS_UNSUPPORTED, "internal: an LDS-pass operation could not be staged");
+        }
     p.dirty = true;
     p.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return Err{};

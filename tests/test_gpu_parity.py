@@ -180,3 +180,17 @@ def test_rotation_folding(q, prec):
         for fold in (1, -1, 0):
             got, _ = run_gpu(q, c, prec, fold_rotations=fold)
             check_state(got, ref, prec, f"{c.name} fold={fold}")
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_wide_blocks_sharing_a_pass(q, prec):
+    """A 6-qubit block and 5-qubit blocks in one LDS pass (the widest keeps
+    its fragments in registers, the others are staged in LDS), on a state of
+    2^20 amplitudes."""
+    rng = W.rng_for(31)
+    mk = lambda qs: W.Gate("dense", tuple(qs), (), (), W.haar_unitary(rng, 2 ** len(qs)))
+    gates = [mk((0, 1, 2, 8, 9, 10)), mk((3, 4, 11, 12, 13)), mk((1, 5, 8, 11, 14)), mk((2, 9, 12, 4, 0)),
+             mk((6, 7, 15, 16, 17, 18)), mk((19, 6, 15, 3, 0))]
+    c = W.Circuit(20, gates)
+    got, _ = run_gpu(q, c, prec)
+    check_state(got, orc.run_circuit(c), prec, "wide blocks")
