@@ -42,17 +42,23 @@ struct DevOp {              // 64 bytes
 };
 static_assert(sizeof(DevOp) == 64, "DevOp layout");
 
-#define QOPS_MAX_UP 8
+#define QOPS_MAX_UP 10
+// LDS tile passes hold physical bits 0..3 contiguously (128-byte runs of
+// complex64) and choose every other tile bit; register tile passes hold bits
+// 0..5 in the lanes of a wave.
+#define QOPS_LDS_FIXED_BITS 4
 #define QOPS_MAX_QUBITS_DEV 34
 #define QOPS_MAX_RUNS 12
 
 // Header of one tile pass.  The tile holds 2^L amplitudes: tile positions
-// 0..5 are physical bits 0..5 (one per lane bit), tile position 6+u is
-// physical bit up_phys[u].  The other physical bits index the tile.
+// 0..F-1 are physical bits 0..F-1 and tile position F+u is physical bit
+// up_phys[u], with F = 6 for register tile passes (one lane bit each) and
+// F = QOPS_LDS_FIXED_BITS for LDS tile passes.  The other physical bits
+// index the tile.
 struct PassHdr {
     int32_t n;
     int32_t L;
-    int32_t nup;                    // L - 6
+    int32_t nup;                    // L - F
     int32_t nops;
     int32_t op0;                    // first op in the op array
     uint32_t map0;                  // mapping used for the load

@@ -867,8 +867,9 @@ template <typename T> constexpr int kLdsEpt = sizeof(T) == 4 ? 32 : 16;
 // LDS tile pass, persistent and software-pipelined: a work-group stages the
 // pass's matrix-core fragments and diagonal tables in LDS once, then loops
 // over tiles; while the operations of tile t run on its LDS copy, the loads
-// of the next tile are already in flight into registers.  Tile element
-// e = 256 u + tid has physical bits 0..5 = e & 63 and bit 6+j = up_phys[j].
+// of the next tile are already in flight into registers.  Tile element e has
+// physical bits 0..F-1 = e mod 2^F and bit F+j = up_phys[j]
+// (F = QOPS_LDS_FIXED_BITS).
 // HK > 0: the pass's widest matrix-core block (HK qubits, op hp->hoist) keeps
 // its A fragments in registers for every tile of the work-group; the other
 // matrix-core blocks of the pass have at most 5 qubits.
@@ -901,11 +902,15 @@ tile_lds_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict__
         const DevOp hop = prog[hoist];   // never staged: read from global memory once
         mfma_load_a<HKK, T>(hav, coef + hop.coef, lane, wave);
     }
-    const uint64_t dep_thr = dep_up((uint32_t)(tid >> 6), hp->up_phys, nup);
-    // element 256 u + tid: bit b of u selects physical bit up_phys[2 + b]
+    // element e = 256 u + tid: bits 0..F-1 of tid are physical bits 0..F-1
+    // (F = QOPS_LDS_FIXED_BITS, contiguous in memory), bits F..7 of tid
+    // select up_phys[0 .. 7-F], bit b of u selects up_phys[8-F+b]
+    constexpr int F = QOPS_LDS_FIXED_BITS;
+    const uint32_t tlow = (uint32_t)tid & ((1u << F) - 1u);
+    const uint64_t dep_thr = dep_up((uint32_t)(tid >> F), hp->up_phys, nup);
     uint64_t ub[5];
 #pragma unroll
-    for (int b = 0; b < 5; ++b) ub[b] = (2 + b < nup) ? (1ull << hp->up_phys[2 + b]) : 0ull;
+    for (int b = 0; b < 5; ++b) ub[b] = (8 - F + b < nup) ? (1ull << hp->up_phys[8 - F + b]) : 0ull;
     auto uoff = [&](int u) {
         uint64_t o = 0;
 #pragma unroll
@@ -916,7 +921,7 @@ tile_lds_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict__
     const uint32_t tsw = swz((uint32_t)tid);
     T pr[EPT], pi[EPT];
     auto fetch = [&](uint64_t tile) {
-        const V* __restrict__ src = st + tile_base(tile, hp) + lane + dep_thr;
+        const V* __restrict__ src = st + tile_base(tile, hp) + tlow + dep_thr;
         sfor<EPT>([&](auto uc) {
             constexpr int u = decltype(uc)::value;
             if (256u * u < N) {
@@ -966,7 +971,7 @@ tile_lds_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict__
             __syncthreads();
         }
         {
-            V* __restrict__ dst = st + base + lane + dep_thr;
+            V* __restrict__ dst = st + base + tlow + dep_thr;
             sfor<EPT>([&](auto uc) {
                 constexpr int u = decltype(uc)::value;
                 if (256u * u < N) dst[uoff(u)] = lds[swz(256u * u) ^ tsw];
@@ -1665,7 +1670,7 @@ batch_pass_kernel(const BatchItem* __restrict__ items, int nitems, const BatchCi
                 v.x = (base == 0 && e == 0) ? (T)1 : (T)0;
                 v.y = 0;
             } else {
-                v = st[base + (e & 63u) + dep_up(e >> 6, hp->up_phys, nup)];
+                v = st[base + (e & ((1u << QOPS_LDS_FIXED_BITS) - 1u)) + dep_up(e >> QOPS_LDS_FIXED_BITS, hp->up_phys, nup)];
             }
             lds[swz(e)] = v;
         }
@@ -1682,7 +1687,7 @@ batch_pass_kernel(const BatchItem* __restrict__ items, int nitems, const BatchCi
             else if (op.type == OP_DIAG_LDS) diag_lds<T>(lds, L, op, cf, base, tid, 256);
             __syncthreads();
         }
-        for (uint32_t e = tid; e < N; e += 256) st[base + (e & 63u) + dep_up(e >> 6, hp->up_phys, nup)] = lds[swz(e)];
+        for (uint32_t e = tid; e < N; e += 256) st[base + (e & ((1u << QOPS_LDS_FIXED_BITS) - 1u)) + dep_up(e >> QOPS_LDS_FIXED_BITS, hp->up_phys, nup)] = lds[swz(e)];
         __syncthreads();
     }
 }

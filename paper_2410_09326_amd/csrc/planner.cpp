@@ -525,10 +525,10 @@ static int push_mfma_coef(Plan& p, const std::vector<cd>& u, int k)
     return off;
 }
 
-static void fill_runs(int n, const std::vector<int>& up, PassHdr& h)
+static void fill_runs(int n, int fixed, const std::vector<int>& up, PassHdr& h)
 {
     std::vector<bool> intile(n, false);
-    for (int b = 0; b < std::min(n, 6); ++b) intile[b] = true;
+    for (int b = 0; b < std::min(n, fixed); ++b) intile[b] = true;
     for (int u : up) intile[u] = true;
     h.nruns = 0;
     int g = 0;
@@ -700,7 +700,7 @@ static void emit_tile_reg(Plan& p, PassPlan& pp)
     h.nup = U;
     h.map0 = map;
     for (int u = 0; u < U; ++u) h.up_phys[u] = up[u];
-    fill_runs(p.n, up, h);
+    fill_runs(p.n, 6, up, h);
     h.op0 = (int)p.dops.size();
     auto regbit = [&](int u) {
         for (int b = 0; b < R; ++b)
@@ -834,12 +834,12 @@ static void emit_tile_lds(Plan& p, PassPlan& pp)
     h.L = pp.L;
     h.nup = (int)pp.up.size();
     for (int u = 0; u < h.nup; ++u) h.up_phys[u] = pp.up[u];
-    fill_runs(p.n, pp.up, h);
+    fill_runs(p.n, QOPS_LDS_FIXED_BITS, pp.up, h);
     h.op0 = (int)p.dops.size();
     auto tpos = [&](int phys) {
-        if (phys < 6) return phys;
+        if (phys < QOPS_LDS_FIXED_BITS) return phys;
         for (int u = 0; u < h.nup; ++u)
-            if (pp.up[u] == phys) return 6 + u;
+            if (pp.up[u] == phys) return QOPS_LDS_FIXED_BITS + u;
         return -1;
     };
     for (int li : pp.lop) emit_lds_op(p, p.lops[li], pp.L, tpos, pp);
@@ -941,21 +941,25 @@ static void finish_pass(Plan& p, PassPlan& pp, uint64_t upmask, bool dense)
 {
     const int n = p.n;
     const double sz = p.prec == 0 ? 8.0 : 16.0;
-    int cap;
+    int cap, fixed;
     if (dense) {
         pp.type = PASS_TILE_LDS;
-        cap = std::min(p.par.L_lds, n) - 6;
+        fixed = QOPS_LDS_FIXED_BITS;
+        cap = std::min(p.par.L_lds, n) - fixed;
     } else {
         pp.type = PASS_TILE_REG;
+        fixed = 6;
         cap = pp.R + pp.W;
     }
+    // the bits the ops need, then the lowest free bits (longer contiguous
+    // runs in memory)
     pp.up.clear();
-    for (int b = 6; b < n; ++b)
+    for (int b = fixed; b < n; ++b)
         if (upmask & (1ull << b)) pp.up.push_back(b);
-    for (int b = 6; b < n && (int)pp.up.size() < cap; ++b)
+    for (int b = fixed; b < n && (int)pp.up.size() < cap; ++b)
         if (!(upmask & (1ull << b))) pp.up.push_back(b);
     std::sort(pp.up.begin(), pp.up.end());
-    pp.L = 6 + (int)pp.up.size();
+    pp.L = fixed + (int)pp.up.size();
     pp.bytes_alg = 2.0 * std::ldexp(1.0, n) * sz;
     if (pp.type == PASS_TILE_LDS) emit_tile_lds(p, pp);
     else emit_tile_reg(p, pp);
@@ -1022,24 +1026,26 @@ static void pack(Plan& p)
     int R, W;
     pick_reg_variant(n, p.prec, p.par.R + p.par.W, R, W);
     const int cap_reg = R + W;
-    const int cap_lds = std::min(p.par.L_lds, n) - 6;
+    const int cap_lds = std::min(p.par.L_lds, n) - QOPS_LDS_FIXED_BITS;
     PassPlan cur;
     cur.R = R;
     cur.W = W;
-    uint64_t S = 0;
+    uint64_t S = 0;           // needed bits beyond a register tile's six fixed ones
+    uint64_t S4 = 0;          //   and beyond an LDS tile's fixed ones
     bool dense = false;
     size_t staged = 0;        // LDS bytes of the staged coefficients
     int hoist_k = 0;          // complex64: qubits of the block kept in registers
     size_t hoist_bytes = 0;   //   and its fragment bytes
     auto flush = [&]() {
         if (!cur.lop.empty()) {
-            finish_pass(p, cur, S, dense);
+            finish_pass(p, cur, dense ? S4 : S, dense);
             p.passes.push_back(cur);
         }
         cur = PassPlan();
         cur.R = R;
         cur.W = W;
         S = 0;
+        S4 = 0;
         dense = false;
         staged = 0;
         hoist_k = 0;
@@ -1054,21 +1060,22 @@ static void pack(Plan& p)
     const size_t nl = p.lops.size();
     const size_t window = 256;
     std::vector<char> placed(nl, 0);
-    auto need_of = [](const LOp& o) {
+    // non-diagonal target bits outside the fixed bits of a register tile (6)
+    // or of an LDS tile (4)
+    auto need_of = [](const LOp& o, int fixed) {
         uint64_t need = 0;
         if (o.kind != LOp::DIAG)
             for (int j = 0; j < o.k; ++j)
-                if (o.t[j] >= 6) need |= 1ull << o.t[j];
+                if (o.t[j] >= fixed) need |= 1ull << o.t[j];
         return need;
     };
     // the op joins the current pass if its bits fit (and, for complex128, its
     // staged fragments fit next to the tile)
     auto try_add = [&](size_t i) -> bool {
         const LOp& o = p.lops[i];
-        const uint64_t need = need_of(o);
+        const uint64_t need6 = need_of(o, 6), need4 = need_of(o, QOPS_LDS_FIXED_BITS);
         const bool d2 = dense || o.kind == LOp::DENSE || p.par.force_lds;
-        const int cap = d2 ? cap_lds : cap_reg;
-        const int Lt = 6 + cap_lds;
+        const int Lt = QOPS_LDS_FIXED_BITS + cap_lds;
         const size_t sb = staged_bytes(p, o, Lt);
         const size_t tile_bytes = (size_t(1) << Lt) * (p.prec == 0 ? 8 : 16);
         size_t nstaged = staged + sb;
@@ -1099,9 +1106,12 @@ static void pack(Plan& p)
             // work-group per CU)
             lds_full = d2 && staged + sb + tile_bytes > lds_budget(p.prec) && sb > 0 && staged > 0;
         }
-        if (!cur.lop.empty() && (__builtin_popcountll(S | need) > cap || lds_full)) return false;
+        const int width = d2 ? __builtin_popcountll(S4 | need4) : __builtin_popcountll(S | need6);
+        const int cap = d2 ? cap_lds : cap_reg;
+        if (!cur.lop.empty() && (width > cap || lds_full)) return false;
         cur.lop.push_back((int)i);
-        S |= need;
+        S |= need6;
+        S4 |= need4;
         dense = d2;
         if (p.prec == 0 && nhoist != hoist_k) hoist_bytes = staged_bytes(p, o, Lt);
         hoist_k = nhoist;
@@ -1244,8 +1254,12 @@ Err build_plan(int n, int prec, const int32_t* l2p_in, const qops_gate* g, size_
         fuse_blocks(p.lops, std::min(par.max_fuse_k, 6));
     }
     pack(p);
-    // complex64 LDS tile kernels read every coefficient but the hoisted
-    // block's from LDS: each such op must have been staged
+    // LDS tile kernels start each of their 256 threads on a distinct tile
+    // element (tiles of at least 2^8); complex64 ones read every coefficient
+    // but the hoisted block's from LDS, so each such op must be staged
+    for (const PassPlan& pp : p.passes)
+        if (pp.type == PASS_TILE_LDS && pp.L < 8)
+            return mkerr(QOPS_UNSUPPORTED, "internal: LDS tile of fewer than 2^8 amplitudes");
     if (p.prec == 0)
         for (const PassPlan& pp : p.passes) {
             if (pp.type != PASS_TILE_LDS) continue;
