@@ -360,36 +360,148 @@ __device__ void diag_lds(typename CxT<T>::V* lds, int L, const DevOp& op, const 
 // linearity turns every address into one XOR of a per-lane and a uniform part.
 template <int K, typename T>
 struct MfmaShape {
-    static constexpr int KS = 1 << (K - 1);    // k-steps of 4 real rows
-    static constexpr int RB = 1 << (K - 3);    // row blocks of 16 real rows
-    static constexpr int RW = K <= 4 ? 1 : (K == 5 ? 2 : 4);
-    static constexpr int CW = 4 / RW;          // column groups
-    static constexpr int RPW = RB / RW;        // row blocks per wave
-    // column blocks in flight (one barrier per chunk if RW > 1): eight
-    // independent accumulator chains per wave
-    static constexpr int CH = RPW >= 4 ? 2 : 4;
+    // K = 3: the real embedding (2^(K+1) real rows, re/im interleaved).
+    // K >= 4: Gauss's three-product form on complex rows: with U = A + iB
+    // and a column x + iy, T1 = A x, T2 = B y, T3 = (A + B)(x + y) give
+    // Re = T1 - T2 and Im = T3 - T1 - T2 (3/4 of the real embedding's MFMAs)
+    static constexpr bool G = K >= 4;
+    static constexpr int KS = G ? 1 << (K - 2) : 1 << (K - 1);   // k-steps of 4 rows
+    static constexpr int RB = G ? 1 << (K - 4) : 1 << (K - 3);   // row blocks of 16 rows
+    static constexpr int RW = G ? RB : 1;                        // waves per column group
+    static constexpr int CW = 4 / RW;                            // column groups
+    static constexpr int RPW = RB / RW;                          // row blocks per wave
+    static constexpr int NF = G ? 3 : RPW;                       // fragment sets per wave
+    // column blocks in flight (one barrier per chunk if RW > 1)
+    static constexpr int CH = 4;
 };
 
 // The A fragments of a wave's row blocks (registers).
 template <int K, typename T>
-using MfmaFrag = T[MfmaShape<K, T>::RPW][MfmaShape<K, T>::KS];
+using MfmaFrag = T[MfmaShape<K, T>::NF][MfmaShape<K, T>::KS];
 
-// The A fragments of the wave's row blocks, from global memory or LDS.
+// The A fragments of the wave's row blocks, from global memory or LDS
+// (Gauss form: A, B and A + B of the wave's row block, per k-step).
 template <int K, typename T>
 __device__ __forceinline__ void mfma_load_a(MfmaFrag<K, T>& av, const T* __restrict__ A, int lane, int wave)
 {
     using S = MfmaShape<K, T>;
     const int rg = wave % S::RW;
+    if constexpr (S::G) {
 #pragma unroll
-    for (int r = 0; r < S::RPW; ++r)
+        for (int ks = 0; ks < S::KS; ++ks)
 #pragma unroll
-        for (int ks = 0; ks < S::KS; ++ks) av[r][ks] = A[((rg * S::RPW + r) * S::KS + ks) * 64 + lane];
+            for (int m = 0; m < 3; ++m) av[m][ks] = A[((rg * S::KS + ks) * 3 + m) * 64 + lane];
+    } else {
+#pragma unroll
+        for (int r = 0; r < S::RPW; ++r)
+#pragma unroll
+            for (int ks = 0; ks < S::KS; ++ks) av[r][ks] = A[((rg * S::RPW + r) * S::KS + ks) * 64 + lane];
+    }
+}
+
+// Gauss form of a 2^K x 2^K complex block (K >= 4): wave (rb, cg) computes
+// complex rows 16 rb .. 16 rb + 15 of its columns.  The B operand of lane l
+// in k-step ks is input 4 ks + l/16 of column l%16, read as one (re, im)
+// pair; the result rows 4(l/16) + i, i < 4, of column l%16 come back in
+// registers i of the three accumulators.
+template <int K, typename T>
+__device__ __forceinline__ void mfma_core_gauss(typename CxT<T>::V* lds, int L, const DevOp& op,
+                                                const MfmaFrag<K, T>& av, int lane, int wave)
+{
+    using V = typename CxT<T>::V;
+    using A4 = typename CxT<T>::A4;
+    using S = MfmaShape<K, T>;
+    constexpr int KS = S::KS, RW = S::RW, CW = S::CW, CH = S::CH;
+    const int rb = wave % RW, cg = wave / RW;
+    const int ncb = 1 << (L - K - 4);
+    const int nper = (ncb + CW - 1) / CW;      // same for every wave
+    uint32_t bit[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) bit[j] = 1u << op.pos[j];
+    const uint32_t gl = deposit_bits((uint32_t)(lane & 15), op.c_lane);
+    auto toff = [&](uint32_t s) {              // s is a compile-time constant or lane-uniform
+        uint32_t o = 0;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (s & (1u << j)) o |= bit[j];
+        return o;
+    };
+    const uint32_t krow = (uint32_t)(lane >> 4);
+    const uint32_t in_sw = swz(toff(krow));                 // input bits 0, 1
+    const uint32_t out_sw = swz(toff(4u * krow)) ^ swz(toff(16u * (uint32_t)rb));
+    const uint32_t wmask = op.c_wave;
+    const uint32_t wstep = deposit_bits((uint32_t)CW, wmask);
+    uint32_t gblk = deposit_bits((uint32_t)cg, wmask);
+    auto mfma = [](const T a, const T b, const A4 c) -> A4 {
+        if constexpr (sizeof(T) == 4) return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+        else return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    };
+    for (int i0 = 0; i0 < nper; i0 += CH) {
+        A4 d1[CH], d2[CH], d3[CH];
+        uint32_t gsw[CH], gcol[CH], gin[CH];
+        bool ok[CH];
+        sfor<CH>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            const int blk = cg + (i0 + c) * CW;
+            ok[c] = i0 + c < nper && blk < ncb;
+            d1[c] = A4{0, 0, 0, 0};
+            d2[c] = A4{0, 0, 0, 0};
+            d3[c] = A4{0, 0, 0, 0};
+            gcol[c] = gl | gblk;
+            gsw[c] = swz(gcol[c]);
+            gin[c] = gsw[c] ^ in_sw;
+            gblk = ((gblk | ~wmask) + wstep) & wmask;
+        });
+        V bq[2][CH];
+        sfor<CH>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            bq[0][c] = lds[gin[c]];
+        });
+        sfor<KS>([&](auto kc) {
+            constexpr int ks = decltype(kc)::value;
+            constexpr int cur = ks & 1;
+            if constexpr (ks + 1 < KS) {
+                const uint32_t nx = swz(toff((uint32_t)(4 * (ks + 1))));
+                sfor<CH>([&](auto cc) {
+                    constexpr int c = decltype(cc)::value;
+                    bq[cur ^ 1][c] = lds[gin[c] ^ nx];
+                });
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            sfor<CH>([&](auto cc) {
+                constexpr int c = decltype(cc)::value;
+                const T x = bq[cur][c].x, y = bq[cur][c].y;
+                d1[c] = mfma(av[0][ks], x, d1[c]);
+                d2[c] = mfma(av[1][ks], y, d2[c]);
+                d3[c] = mfma(av[2][ks], x + y, d3[c]);
+            });
+            __builtin_amdgcn_sched_barrier(0);
+        });
+        if constexpr (RW > 1) __syncthreads();   // the chunk's inputs are read
+        sfor<CH>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            if (ok[c] && (gcol[c] & op.c_tile) == op.c_tile) {
+                const uint32_t g_out = gsw[c] ^ out_sw;
+                sfor<4>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    V w;
+                    w.x = d1[c][i] - d2[c][i];
+                    w.y = d3[c][i] - d1[c][i] - d2[c][i];
+                    lds[g_out ^ swz(toff((uint32_t)i))] = w;
+                });
+            }
+        });
+    }
 }
 
 template <int K, typename T>
 __device__ __forceinline__ void mfma_core(typename CxT<T>::V* lds, int L, const DevOp& op, const MfmaFrag<K, T>& av,
                                           int lane, int wave)
 {
+    if constexpr (MfmaShape<K, T>::G) {
+        mfma_core_gauss<K, T>(lds, L, op, av, lane, wave);
+        return;
+    } else {
     using V = typename CxT<T>::V;
     using A4 = typename CxT<T>::A4;
     using S = MfmaShape<K, T>;
@@ -489,6 +601,7 @@ __device__ __forceinline__ void mfma_core(typename CxT<T>::V* lds, int L, const 
                 }
             }
         });
+    }
     }
 }
 

@@ -502,9 +502,32 @@ static int push_coef(Plan& p, const std::vector<cd>& m)
 // register i; the f64 one returns row l/16 + 4*i.  For f64 the A rows are
 // permuted (rho(x) = 4*(x%4) + x/4) so that both land in the same place and
 // the kernel's write-back is shared.
+// Coefficients of a matrix-core block: k = 3 uses the real embedding
+// (2^(k+1) square, 4^(k+1) values), k >= 4 Gauss's three-product form (the
+// real part, the imaginary part and their sum of each k-step fragment,
+// 3 * 4^k values).
+static size_t mfma_coef_count(int k) { return k >= 4 ? size_t(3) << (2 * k) : size_t(1) << (2 * (k + 1)); }
+
 static int push_mfma_coef(Plan& p, const std::vector<cd>& u, int k)
 {
     const int d = 1 << k, D = 2 * d;
+    if (k >= 4) {
+        // fragment (rb, ks, m), lane l: row 16 rb + x (x = l % 16, permuted for
+        // the FP64 result layout), column 4 ks + l / 16, of A (m = 0), B (1) or
+        // A + B (2), composed in FP64
+        const int KS = d / 4, RB = d / 16;
+        const int off = (int)p.coef.size();
+        for (int rb = 0; rb < RB; ++rb)
+            for (int ks = 0; ks < KS; ++ks)
+                for (int m = 0; m < 3; ++m)
+                    for (int l = 0; l < 64; ++l) {
+                        const int x = l & 15;
+                        const int row = p.prec == QOPS_C64 ? x : 4 * (x & 3) + (x >> 2);
+                        const cd v = u[(size_t)(16 * rb + row) * d + (4 * ks + (l >> 4))];
+                        p.coef.push_back(m == 0 ? v.real() : (m == 1 ? v.imag() : v.real() + v.imag()));
+                    }
+        return off;
+    }
     const int KS = D / 4, RB = D / 16;
     auto Mre = [&](int r, int c) -> double {
         const cd v = u[(size_t)(r >> 1) * d + (c >> 1)];
@@ -804,7 +827,7 @@ static size_t staged_bytes(const Plan& p, const LOp& o, int L)
     const size_t sz = p.prec == 0 ? 4 : 8;
     if (o.kind == LOp::DIAG) return (size_t(2) << o.k) * sz;
     const int k = o.kind == LOp::PSWAP ? 2 : o.k;
-    if (o.kind == LOp::DENSE && use_mfma_for(p, k, L)) return (size_t(1) << (2 * (k + 1))) * sz;
+    if (o.kind == LOp::DENSE && use_mfma_for(p, k, L)) return mfma_coef_count(k) * sz;
     return (size_t(2) << (2 * k)) * sz;   // 2^k x 2^k complex for the vector ALU
 }
 
@@ -862,7 +885,7 @@ static void emit_tile_lds(Plan& p, PassPlan& pp)
         if (d.type != OP_MFMA && d.type != OP_DIAG_LDS && d.type != OP_DENSE_LDS) continue;
         if (i - h.op0 == h.hoist) continue;
         size_t cnt;
-        if (d.type == OP_MFMA) cnt = size_t(1) << (2 * (d.a + 1));
+        if (d.type == OP_MFMA) cnt = mfma_coef_count(d.a);
         else if (d.type == OP_DENSE_LDS) cnt = size_t(2) << (2 * d.a);
         else cnt = size_t(2) << d.a;
         if (cnt > room) continue;
