@@ -595,35 +595,79 @@ static bool lds_capable(const Plan& p, const LOp& o, int L)
 // amplitudes (one value of the L-k free tile positions); the 16 columns a
 // wave reads at once differ in four free positions (c_lane), the column
 // block number fills the rest (c_wave).  The LDS swizzle folds tile
-// positions 5..8 onto 0..3, and the 16 lanes of a read hit distinct bank
-// pairs when the four positions fall on distinct residues of that fold, so
-// those are taken first.
+// positions 5..9 onto 0..4, so position p falls in bank class p (p < 5),
+// p - 5 (p < 10) or none.  The 32 lanes of half a wave read 16 columns times
+// the two values of the op's matrix bit 0, and hit distinct banks when those
+// five positions have distinct classes: the op's bit 0 is chosen for a class
+// the columns can avoid, then the columns take distinct classes.
+static int bank_class(int tp) { return tp < 5 ? tp : (tp < 10 ? tp - 5 : -1); }
+
+// Picks up to four free positions (not in opm) with distinct classes other
+// than `avoid`; returns the number of distinct classes reached (with avoid).
+static int pick_columns(uint32_t opm, int L, int avoid, uint32_t& used)
+{
+    int pick[5] = {-1, -1, -1, -1, -1};
+    used = 0;
+    int got = 0;
+    for (int tp = 0; tp < L && got < 4; ++tp) {
+        if (opm & (1u << tp)) continue;
+        const int r = bank_class(tp);
+        if (r >= 0 && r != avoid && pick[r] < 0) {
+            pick[r] = tp;
+            used |= 1u << tp;
+            ++got;
+        }
+    }
+    const int distinct = got + (avoid >= 0 ? 1 : 0);
+    for (int tp = 0; tp < L && __builtin_popcount(used) < 4; ++tp)
+        if (!(opm & (1u << tp)) && !(used & (1u << tp))) used |= 1u << tp;
+    return distinct;
+}
+
 static void set_mfma_columns(DevOp& d, int k, int L)
 {
     uint32_t opm = 0;
     for (int j = 0; j < k; ++j) opm |= 1u << d.pos[j];
-    int pick[4] = {-1, -1, -1, -1};
     uint32_t used = 0;
-    auto bank_class = [](int tp) { return tp < 4 ? tp : (tp >= 5 && tp <= 8 ? tp - 5 : -1); };
-    for (int tp = 0; tp < L; ++tp) {
-        if (opm & (1u << tp)) continue;
-        const int r = bank_class(tp);
-        if (r >= 0 && pick[r] < 0) {
-            pick[r] = tp;
-            used |= 1u << tp;
-        }
-    }
-    for (int i = 0; i < 4; ++i)
-        if (pick[i] < 0)
-            for (int tp = 0; tp < L; ++tp)
-                if (!(opm & (1u << tp)) && !(used & (1u << tp))) {
-                    pick[i] = tp;
-                    used |= 1u << tp;
-                    break;
-                }
+    pick_columns(opm, L, bank_class(d.pos[0]), used);
     const uint32_t all = (L >= 32 ? ~0u : ((1u << L) - 1u));
     d.c_lane = used;
     d.c_wave = all & ~opm & ~used;
+}
+
+// Which target becomes matrix bit 0 of a matrix-core op (see above): the one
+// whose class lets the columns and it cover the most distinct classes
+// (ties keep the lower index).
+static int best_bit0(const int* tp, int k, int L)
+{
+    uint32_t opm = 0;
+    for (int j = 0; j < k; ++j) opm |= 1u << tp[j];
+    int best = 0, score = -1;
+    for (int j = 0; j < k; ++j) {
+        uint32_t used;
+        const int sc = pick_columns(opm, L, bank_class(tp[j]), used);
+        if (sc > score) {
+            score = sc;
+            best = j;
+        }
+    }
+    return best;
+}
+
+// Exchanges matrix bits 0 and j of a 2^k x 2^k matrix (and the targets).
+static void swap_matrix_bits(std::vector<cd>& m, int* t, int k, int j)
+{
+    if (j == 0) return;
+    const int d = 1 << k;
+    auto sw = [&](int x) {
+        const int b0 = x & 1, bj = (x >> j) & 1;
+        return (x & ~1 & ~(1 << j)) | (bj) | (b0 << j);
+    };
+    std::vector<cd> r((size_t)d * d);
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) r[(size_t)sw(a) * d + sw(b)] = m[(size_t)a * d + b];
+    m.swap(r);
+    std::swap(t[0], t[j]);
 }
 
 template <typename F>
@@ -652,6 +696,11 @@ static void emit_lds_op(Plan& p, const LOp& o, int L, F tpos, PassPlan& pp)
             m[1 * 4 + 2] = 1;
             m[2 * 4 + 1] = 1;
             m[15] = 1;
+        }
+        if (o.kind == LOp::DENSE && use_mfma_for(p, k, L)) {
+            int tp[6];
+            for (int j = 0; j < k; ++j) tp[j] = tpos(t[j]);
+            swap_matrix_bits(m, t, k, best_bit0(tp, k, L));
         }
         for (int j = 0; j < k; ++j) d.pos[j] = tpos(t[j]);
         for (int b = 0; b < 64; ++b)
