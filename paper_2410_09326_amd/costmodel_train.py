@@ -65,8 +65,8 @@ def collect(n_circuits: int, seed0: int = 1000, time_budget: float = 240.0, max_
         held = (i % 10) == 9
         if held:
             hold_prof = prof if hold_prof is None else (hold_prof.merge(prof) or hold_prof)
-        elif i % 8 == 0:
-            # the plain cost table is fitted to every 8th training circuit (a
+        elif i % 32 == 0:
+            # the plain cost table is fitted to every 32nd training circuit (a
             # compact profile that ships with the package)
             train_prof = prof if train_prof is None else (train_prof.merge(prof) or train_prof)
         feats.append(f)
