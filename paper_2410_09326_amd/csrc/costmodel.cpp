@@ -149,8 +149,6 @@ int32_t build_priced_plan(int n, int prec, const int32_t* l2p, const qops_gate* 
     return QOPS_OK;
 }
 
-void destroy_profiling(qops_sim*) {}
-
 }  // namespace qops
 
 extern "C" {

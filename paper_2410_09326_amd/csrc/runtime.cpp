@@ -263,7 +263,6 @@ int32_t qops_destroy(qops_sim* h)
         free_plan_device(*h->last_plan);
         delete h->last_plan;
     }
-    destroy_profiling(h);
     delete h;
     return QOPS_OK;
 }

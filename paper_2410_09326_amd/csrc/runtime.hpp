@@ -43,6 +43,5 @@ PlanParams params_from(const qops_plan_opts* o, int n, int prec);
 // profile's cost table or the trained model and keep the cheapest.
 int32_t build_priced_plan(int n, int prec, const int32_t* l2p, const qops_gate* g, size_t ng,
                           const qops_plan_opts* opts, Plan& out);
-void destroy_profiling(qops_sim* h);
 
 }  // namespace qops
