@@ -9,7 +9,11 @@ properties that hold at any size (the FP64 oracle cannot hold these states):
   every sampled amplitude equals 2^(-n/2) exp(2 pi i x y / 2^n), the phase
   taken from the exact integer product;
 * the 512-circuit parameter sweep as one batch: <Z> of sampled circuits
-  against the oracle (n <= 16) and against the complex128 single-circuit path.
+  against the oracle (n <= 16) and against the complex128 single-circuit path;
+* 28-qubit QFT + 40 U3/CZ layers, both swap modes: complex64 against
+  complex128 and the inverse circuit returning the seeded basis state;
+* a 32-qubit depth-60 evaluation circuit under the learned and the plain
+  cost-model plans: <Z_i> against the complex128 run.
 """
 import numpy as np
 import pytest
@@ -119,3 +123,59 @@ def test_param_sweep_batch_full(q):
         sim.run(q.Plan(circs[i].n, spec[i][1], precision=q.C128))
         assert np.max(np.abs(res[i] - sim.expect_z())) <= 2e-5, (i, circs[i].n)
         sim.close()
+
+
+@pytest.mark.parametrize("swap_mode", [0, 1])
+def test_qft28_layers_c64_c128_and_inverse(q, swap_mode):
+    """The 28-qubit QFT + 40 U3/CZ layers workload at full size, both swap
+    modes: complex64 against complex128 on the GPU, and the complex128 state
+    followed by the inverse circuit returning the seeded basis state."""
+    import torch
+    c = W.qft_then_layers(1, n=28, layers=40)
+    sims = {}
+    for prec in (q.C64, q.C128):
+        sim = q.Simulator(28, prec)
+        sim.init_basis(c.x0)
+        sim.run(q.Plan(28, c.gates, precision=prec, swap_mode=swap_mode))
+        sims[prec] = sim
+    assert np.array_equal(sims[q.C64].layout(), sims[q.C128].layout())
+    assert abs(sims[q.C64].norm() - 1) < 1e-5 and abs(sims[q.C128].norm() - 1) < 1e-12
+    a = _as_complex(q, sims[q.C64]).to(torch.complex128)
+    b = _as_complex(q, sims[q.C128])
+    err = float((a - b).abs().max())
+    # fidelity of the normalised states: the complex64 norm drift is bounded
+    # on its own above
+    fid = abs(complex(torch.vdot(b, a).item())) ** 2 / (
+        float(torch.vdot(a, a).real) * float(torch.vdot(b, b).real))
+    del a
+    assert err <= 2e-5 and 1 - fid <= 1e-6, (err, fid)
+    s = sims[q.C128]
+    s.run(q.Plan(28, W.inverse(c).gates, precision=q.C128, swap_mode=swap_mode, l2p=s.layout()))
+    z = _as_complex(q, s)
+    l2p = s.layout()
+    phys0 = sum(1 << int(l2p[k]) for k in range(28) if (c.x0 >> k) & 1)
+    assert abs(complex(z[phys0].item()) - 1.0) <= 1e-10
+    for sim in sims.values():
+        sim.close()
+
+
+def test_eval32_priced_plans_agree_with_c128(q):
+    """A 32-qubit depth-60 evaluation circuit: the plans the learned and the
+    plain cost models pick (complex64) give the <Z_i> of the complex128 run."""
+    import os
+    here = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    models = os.path.join(here, "paper_2410_09326_amd", "models")
+    model = q.CostModel.load(os.path.join(models, "cost_mlp.bin"))
+    prof = q.Profile.load(os.path.join(models, "corpus_profile.bin"))
+    c = W.eval_circuit(9000, n=32, depth=60)
+    ref = q.Simulator(32, q.C128)
+    ref.init_basis(0)
+    ref.run(q.Plan(32, c.gates, precision=q.C128))
+    zref = ref.expect_z()
+    ref.close()
+    sim = q.Simulator(32, q.C64)
+    for mode, kw in ((q.PLAN_LEARNED, {"model": model}), (q.PLAN_PROFILED, {"profile": prof})):
+        sim.init_basis(0)
+        sim.run(q.Plan(32, c.gates, precision=q.C64, mode=mode, **kw))
+        assert np.max(np.abs(sim.expect_z() - zref)) <= 1e-5
+    sim.close()
