@@ -457,6 +457,10 @@ __device__ __forceinline__ void mfma_core_gauss(typename CxT<T>::V* lds, int L, 
             constexpr int c = decltype(cc)::value;
             bq[0][c] = lds[gin[c]];
         });
+        // issue priority over the other work-group's waves on this SIMD
+        // while the wave streams MFMAs (their tile loads, stores and
+        // write-backs fill the matrix core's gaps instead of delaying it)
+        __builtin_amdgcn_s_setprio(1);
         sfor<KS>([&](auto kc) {
             constexpr int ks = decltype(kc)::value;
             constexpr int cur = ks & 1;
@@ -477,6 +481,7 @@ __device__ __forceinline__ void mfma_core_gauss(typename CxT<T>::V* lds, int L, 
             });
             __builtin_amdgcn_sched_barrier(0);
         });
+        __builtin_amdgcn_s_setprio(0);
         if constexpr (RW > 1) __syncthreads();   // the chunk's inputs are read
         sfor<CH>([&](auto cc) {
             constexpr int c = decltype(cc)::value;
@@ -562,6 +567,10 @@ __device__ __forceinline__ void mfma_core(typename CxT<T>::V* lds, int L, const 
             constexpr int c = decltype(cc)::value;
             bq[0][c] = ldsf[2 * (gin[c] ^ swz(toff(0u))) + part];
         });
+        // issue priority over the other work-group's waves on this SIMD
+        // while the wave streams MFMAs (their tile loads, stores and
+        // write-backs fill the matrix core's gaps instead of delaying it)
+        __builtin_amdgcn_s_setprio(1);
         sfor<KS>([&](auto kc) {
             constexpr int ks = decltype(kc)::value;
             constexpr int cur = ks & 1;
@@ -582,6 +591,7 @@ __device__ __forceinline__ void mfma_core(typename CxT<T>::V* lds, int L, const 
             });
             __builtin_amdgcn_sched_barrier(0);
         });
+        __builtin_amdgcn_s_setprio(0);
         if constexpr (RW > 1) __syncthreads();   // the chunk's B fragments are read
         sfor<CH>([&](auto cc) {
             constexpr int c = decltype(cc)::value;
@@ -986,7 +996,12 @@ template <typename T> constexpr int kLdsEpt = sizeof(T) == 4 ? 32 : 16;
 // HK > 0: the pass's widest matrix-core block (HK qubits, op hp->hoist) keeps
 // its A fragments in registers for every tile of the work-group; the other
 // matrix-core blocks of the pass have at most 5 qubits.
-template <typename T, int HK>
+// FULL: the tile has the largest size (EPT amplitudes per thread).  Its
+// global loads and stores then carry no branch, so the vector-memory counter
+// sees one fixed order (the next tile's loads, then this tile's stores) and
+// the wait before the LDS fill covers the loads only: the stores drain under
+// the next tile's work.  Smaller tiles test each element and wait for all.
+template <typename T, int HK, bool FULL>
 __global__ void __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1)
 tile_lds_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict__ hp, const DevOp* __restrict__ ops,
                 const T* __restrict__ coef, uint64_t ntiles)
@@ -1037,7 +1052,7 @@ tile_lds_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict__
         const V* __restrict__ src = st + tile_base(tile, hp) + tlow + dep_thr;
         sfor<EPT>([&](auto uc) {
             constexpr int u = decltype(uc)::value;
-            if (256u * u < N) {
+            if (FULL || 256u * u < N) {
                 const V x = src[uoff(u)];
                 pr[u] = x.x;
                 pi[u] = x.y;
@@ -1046,11 +1061,14 @@ tile_lds_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict__
     };
     uint64_t tile = blockIdx.x;
     if (tile < ntiles) fetch(tile);
+    // drain the first fetch here, so that the loop head sees outstanding
+    // loads from the loop body only
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
     for (; tile < ntiles; tile += gridDim.x) {
         const uint64_t base = tile_base(tile, hp);
         sfor<EPT>([&](auto uc) {
             constexpr int u = decltype(uc)::value;
-            if (256u * u < N) {
+            if (FULL || 256u * u < N) {
                 V x;
                 x.x = pr[u];
                 x.y = pi[u];
@@ -1087,7 +1105,7 @@ tile_lds_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict__
             V* __restrict__ dst = st + base + tlow + dep_thr;
             sfor<EPT>([&](auto uc) {
                 constexpr int u = decltype(uc)::value;
-                if (256u * u < N) dst[uoff(u)] = lds[swz(256u * u) ^ tsw];
+                if (FULL || 256u * u < N) dst[uoff(u)] = lds[swz(256u * u) ^ tsw];
             });
         }
         __syncthreads();
@@ -1108,37 +1126,45 @@ static int num_cus()
     return g_num_cus;
 }
 
-template <typename T, int HK>
-static hipError_t launch_tile_lds_t(void* state, const PassHdr* hdr, const DevOp* ops, const void* coef,
+template <typename T, int HK, bool FULL>
+static hipError_t launch_tile_lds_f(void* state, const PassHdr* hdr, const DevOp* ops, const void* coef,
                                     uint64_t grid, uint64_t ntiles, int lds_bytes, hipStream_t s)
 {
     using V = typename CxT<T>::V;
     static bool done = false;
     if (!done) {
-        (void)hipFuncSetAttribute((const void*)tile_lds_kernel<T, HK>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  tile_max_lds_bytes());
+        (void)hipFuncSetAttribute((const void*)tile_lds_kernel<T, HK, FULL>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, tile_max_lds_bytes());
         done = true;
     }
-    hipLaunchKernelGGL((tile_lds_kernel<T, HK>), dim3((unsigned)grid), dim3(256), lds_bytes, s,
+    hipLaunchKernelGGL((tile_lds_kernel<T, HK, FULL>), dim3((unsigned)grid), dim3(256), lds_bytes, s,
                        reinterpret_cast<V*>(state), hdr, ops, reinterpret_cast<const T*>(coef), ntiles);
     return hipGetLastError();
+}
+
+template <typename T, int HK>
+static hipError_t launch_tile_lds_t(void* state, const PassHdr* hdr, const DevOp* ops, const void* coef,
+                                    uint64_t grid, uint64_t ntiles, int L, int lds_bytes, hipStream_t s)
+{
+    constexpr int LMAX = sizeof(T) == 4 ? 13 : 12;   // 256 threads x kLdsEpt<T>
+    if (L == LMAX) return launch_tile_lds_f<T, HK, true>(state, hdr, ops, coef, grid, ntiles, lds_bytes, s);
+    return launch_tile_lds_f<T, HK, false>(state, hdr, ops, coef, grid, ntiles, lds_bytes, s);
 }
 
 hipError_t launch_tile_lds(int prec, void* state, const PassHdr* hdr, const DevOp* ops, const void* coef,
                            uint64_t ntiles, int L, int lds_bytes, int grid_cap, int hoist_k, hipStream_t s)
 {
-    (void)L;
     // persistent grid: as many work-groups as fit on the chip at this LDS size
     const int per_cu = std::max(1, std::min(8, tile_max_lds_bytes() / std::max(lds_bytes, 1)));
     uint64_t grid = std::min<uint64_t>(ntiles, (uint64_t)num_cus() * per_cu);
     if (grid_cap > 0 && grid > (uint64_t)grid_cap) grid = (uint64_t)grid_cap;
     if (grid == 0) grid = 1;
     if (prec == 0) {
-        if (hoist_k == 6) return launch_tile_lds_t<float, 6>(state, hdr, ops, coef, grid, ntiles, lds_bytes, s);
-        if (hoist_k == 5) return launch_tile_lds_t<float, 5>(state, hdr, ops, coef, grid, ntiles, lds_bytes, s);
-        return launch_tile_lds_t<float, 0>(state, hdr, ops, coef, grid, ntiles, lds_bytes, s);
+        if (hoist_k == 6) return launch_tile_lds_t<float, 6>(state, hdr, ops, coef, grid, ntiles, L, lds_bytes, s);
+        if (hoist_k == 5) return launch_tile_lds_t<float, 5>(state, hdr, ops, coef, grid, ntiles, L, lds_bytes, s);
+        return launch_tile_lds_t<float, 0>(state, hdr, ops, coef, grid, ntiles, L, lds_bytes, s);
     }
-    return launch_tile_lds_t<double, 0>(state, hdr, ops, coef, grid, ntiles, lds_bytes, s);
+    return launch_tile_lds_t<double, 0>(state, hdr, ops, coef, grid, ntiles, L, lds_bytes, s);
 }
 
 // ---------------------------------------------------------------------------
