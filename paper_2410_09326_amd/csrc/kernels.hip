@@ -452,10 +452,18 @@ __device__ __forceinline__ void mfma_core_gauss(typename CxT<T>::V* lds, int L, 
             gin[c] = gsw[c] ^ in_sw;
             gblk = ((gblk | ~wmask) + wstep) & wmask;
         });
+        // B values (and x + y) one k-step ahead of the MFMAs that use them:
+        // the sums of step ks + 1 are formed while the MFMAs of step ks run,
+        // so no MFMA waits on the vector ALU result it reads
         V bq[2][CH];
+        T bs[2][CH];
         sfor<CH>([&](auto cc) {
             constexpr int c = decltype(cc)::value;
             bq[0][c] = lds[gin[c]];
+        });
+        sfor<CH>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            bs[0][c] = bq[0][c].x + bq[0][c].y;
         });
         // issue priority over the other work-group's waves on this SIMD
         // while the wave streams MFMAs (their tile loads, stores and
@@ -474,12 +482,18 @@ __device__ __forceinline__ void mfma_core_gauss(typename CxT<T>::V* lds, int L, 
             __builtin_amdgcn_sched_barrier(0);
             sfor<CH>([&](auto cc) {
                 constexpr int c = decltype(cc)::value;
-                const T x = bq[cur][c].x, y = bq[cur][c].y;
-                d1[c] = mfma(av[0][ks], x, d1[c]);
-                d2[c] = mfma(av[1][ks], y, d2[c]);
-                d3[c] = mfma(av[2][ks], x + y, d3[c]);
+                d1[c] = mfma(av[0][ks], bq[cur][c].x, d1[c]);
+                d2[c] = mfma(av[1][ks], bq[cur][c].y, d2[c]);
+                d3[c] = mfma(av[2][ks], bs[cur][c], d3[c]);
             });
             __builtin_amdgcn_sched_barrier(0);
+            if constexpr (ks + 1 < KS) {
+                sfor<CH>([&](auto cc) {
+                    constexpr int c = decltype(cc)::value;
+                    bs[cur ^ 1][c] = bq[cur ^ 1][c].x + bq[cur ^ 1][c].y;
+                });
+                __builtin_amdgcn_sched_barrier(0);
+            }
         });
         __builtin_amdgcn_s_setprio(0);
         if constexpr (RW > 1) __syncthreads();   // the chunk's inputs are read

@@ -598,30 +598,70 @@ static bool lds_capable(const Plan& p, const LOp& o, int L)
 // positions 5..9 onto 0..4, so position p falls in bank class p (p < 5),
 // p - 5 (p < 10) or none.  The 32 lanes of half a wave read 16 columns times
 // the two values of the op's matrix bit 0, and hit distinct banks when those
-// five positions have distinct classes: the op's bit 0 is chosen for a class
-// the columns can avoid, then the columns take distinct classes.
+// five positions have distinct classes.  Writes go the same way with the
+// result rows: half a wave writes 16 columns times the two values of matrix
+// bit 1 (real embedding, k = 3) or bit 2 (three-product form, k >= 4).  The
+// op's targets for these two matrix bits are chosen so that the columns can
+// avoid both classes (best when the two share one), then the columns take
+// distinct classes.
 static int bank_class(int tp) { return tp < 5 ? tp : (tp < 10 ? tp - 5 : -1); }
 
-// Picks up to four free positions (not in opm) with distinct classes other
-// than `avoid`; returns the number of distinct classes reached (with avoid).
-static int pick_columns(uint32_t opm, int L, int avoid, uint32_t& used)
+// Matrix bit whose two values share half a wave in the write-back.
+static int write_bit(int k) { return k >= 4 ? 2 : 1; }
+
+static uint32_t class_bit(int tp)
 {
-    int pick[5] = {-1, -1, -1, -1, -1};
+    const int r = bank_class(tp);
+    return r >= 0 ? 1u << r : 0u;
+}
+
+// Picks up to four free positions (not in opm) with distinct classes outside
+// the classes in `avoid` (a bit mask of classes), then fills up to four.
+static void pick_columns(uint32_t opm, int L, uint32_t avoid, uint32_t& used)
+{
+    uint32_t taken = 0;
     used = 0;
     int got = 0;
     for (int tp = 0; tp < L && got < 4; ++tp) {
         if (opm & (1u << tp)) continue;
-        const int r = bank_class(tp);
-        if (r >= 0 && r != avoid && pick[r] < 0) {
-            pick[r] = tp;
+        const uint32_t c = class_bit(tp);
+        if (c && !(avoid & c) && !(taken & c)) {
+            taken |= c;
             used |= 1u << tp;
             ++got;
         }
     }
-    const int distinct = got + (avoid >= 0 ? 1 : 0);
     for (int tp = 0; tp < L && __builtin_popcount(used) < 4; ++tp)
         if (!(opm & (1u << tp)) && !(used & (1u << tp))) used |= 1u << tp;
-    return distinct;
+}
+
+// Distinct bank classes among the column positions and one more position.
+static int distinct_classes(uint32_t used, int extra)
+{
+    uint32_t m = class_bit(extra);
+    for (int tp = 0; tp < 32; ++tp)
+        if (used & (1u << tp)) m |= class_bit(tp);
+    return __builtin_popcount(m);
+}
+
+// Columns for an op whose read and write bits sit at tile positions t0, tw:
+// avoiding both classes, or only one of them (four free classes for the
+// columns can beat three); returns the distinct classes reached, reads plus
+// writes (ties keep the earlier choice).
+static int best_columns(uint32_t opm, int L, int t0, int tw, uint32_t& used)
+{
+    const uint32_t masks[3] = {class_bit(t0) | class_bit(tw), class_bit(t0), class_bit(tw)};
+    int best = -1;
+    for (uint32_t av : masks) {
+        uint32_t u;
+        pick_columns(opm, L, av, u);
+        const int sc = distinct_classes(u, t0) + distinct_classes(u, tw);
+        if (sc > best) {
+            best = sc;
+            used = u;
+        }
+    }
+    return best;
 }
 
 static void set_mfma_columns(DevOp& d, int k, int L)
@@ -629,45 +669,59 @@ static void set_mfma_columns(DevOp& d, int k, int L)
     uint32_t opm = 0;
     for (int j = 0; j < k; ++j) opm |= 1u << d.pos[j];
     uint32_t used = 0;
-    pick_columns(opm, L, bank_class(d.pos[0]), used);
+    best_columns(opm, L, d.pos[0], d.pos[write_bit(k)], used);
     const uint32_t all = (L >= 32 ? ~0u : ((1u << L) - 1u));
     d.c_lane = used;
     d.c_wave = all & ~opm & ~used;
 }
 
-// Which target becomes matrix bit 0 of a matrix-core op (see above): the one
-// whose class lets the columns and it cover the most distinct classes
-// (ties keep the lower index).
-static int best_bit0(const int* tp, int k, int L)
+// Which targets become matrix bit 0 (reads) and the write bit: the pair that
+// reaches the most distinct classes (ties keep the lower indices).
+static void best_bank_bits(const int* tp, int k, int L, int& j0, int& jw)
 {
     uint32_t opm = 0;
     for (int j = 0; j < k; ++j) opm |= 1u << tp[j];
-    int best = 0, score = -1;
-    for (int j = 0; j < k; ++j) {
-        uint32_t used;
-        const int sc = pick_columns(opm, L, bank_class(tp[j]), used);
-        if (sc > score) {
-            score = sc;
-            best = j;
+    int score = -1;
+    j0 = 0;
+    jw = write_bit(k);
+    for (int a = 0; a < k; ++a)
+        for (int b = 0; b < k; ++b) {
+            if (a == b) continue;
+            uint32_t used;
+            const int sc = best_columns(opm, L, tp[a], tp[b], used);
+            if (sc > score) {
+                score = sc;
+                j0 = a;
+                jw = b;
+            }
         }
-    }
-    return best;
 }
 
-// Exchanges matrix bits 0 and j of a 2^k x 2^k matrix (and the targets).
-static void swap_matrix_bits(std::vector<cd>& m, int* t, int k, int j)
+// Exchanges matrix bits p and q of a 2^k x 2^k matrix (and the targets).
+static void swap_matrix_bits(std::vector<cd>& m, int* t, int k, int p, int q)
 {
-    if (j == 0) return;
+    if (p == q) return;
     const int d = 1 << k;
     auto sw = [&](int x) {
-        const int b0 = x & 1, bj = (x >> j) & 1;
-        return (x & ~1 & ~(1 << j)) | (bj) | (b0 << j);
+        const int bp = (x >> p) & 1, bq = (x >> q) & 1;
+        return (x & ~(1 << p) & ~(1 << q)) | (bp << q) | (bq << p);
     };
     std::vector<cd> r((size_t)d * d);
     for (int a = 0; a < d; ++a)
         for (int b = 0; b < d; ++b) r[(size_t)sw(a) * d + sw(b)] = m[(size_t)a * d + b];
     m.swap(r);
-    std::swap(t[0], t[j]);
+    std::swap(t[p], t[q]);
+}
+
+// Moves targets j0 and jw (j0 != jw) to matrix bits 0 and the write bit.
+static void place_bank_bits(std::vector<cd>& m, int* t, int* tp, int k, int j0, int jw)
+{
+    const int w = write_bit(k);
+    swap_matrix_bits(m, t, k, 0, j0);
+    std::swap(tp[0], tp[j0]);
+    if (jw == 0) jw = j0;   // that target now sits where the bit-0 one was
+    swap_matrix_bits(m, t, k, w, jw);
+    std::swap(tp[w], tp[jw]);
 }
 
 template <typename F>
@@ -700,7 +754,9 @@ static void emit_lds_op(Plan& p, const LOp& o, int L, F tpos, PassPlan& pp)
         if (o.kind == LOp::DENSE && use_mfma_for(p, k, L)) {
             int tp[6];
             for (int j = 0; j < k; ++j) tp[j] = tpos(t[j]);
-            swap_matrix_bits(m, t, k, best_bit0(tp, k, L));
+            int j0 = 0, jw = 1;
+            best_bank_bits(tp, k, L, j0, jw);
+            place_bank_bits(m, t, tp, k, j0, jw);
         }
         for (int j = 0; j < k; ++j) d.pos[j] = tpos(t[j]);
         for (int b = 0; b < 64; ++b)
