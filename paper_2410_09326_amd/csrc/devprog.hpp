@@ -47,6 +47,10 @@ static_assert(sizeof(DevOp) == 64, "DevOp layout");
 // complex64) and choose every other tile bit; register tile passes hold bits
 // 0..5 in the lanes of a wave.
 #define QOPS_LDS_FIXED_BITS 4
+// LDS of one work-group of the LDS tile kernel (tile plus staged
+// coefficients): complex64 runs two work-groups per CU, complex128 one.
+#define QOPS_LDS_TILE_BYTES_C64 (80 * 1024)
+#define QOPS_LDS_TILE_BYTES_C128 (160 * 1024)
 #define QOPS_MAX_QUBITS_DEV 34
 #define QOPS_MAX_RUNS 12
 

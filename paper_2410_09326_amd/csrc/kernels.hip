@@ -358,6 +358,19 @@ __device__ void diag_lds(typename CxT<T>::V* lds, int L, const DevOp& op, const 
 // holds real row 4(l/16)+i of column l%16; the B operand of lane l is real
 // row 4 ks + l/16 of column l%16.  LDS slots are swizzled (swz), whose
 // linearity turns every address into one XOR of a per-lane and a uniform part.
+// LDS element access by byte offset (the XOR-swizzled addresses of the
+// matrix-core loops are formed on byte offsets, one XOR per access).
+template <typename V>
+__device__ __forceinline__ V lds_at(const V* lds, uint32_t off)
+{
+    return *reinterpret_cast<const V*>(reinterpret_cast<const unsigned char*>(lds) + off);
+}
+template <typename V>
+__device__ __forceinline__ void lds_put(V* lds, uint32_t off, const V& v)
+{
+    *reinterpret_cast<V*>(reinterpret_cast<unsigned char*>(lds) + off) = v;
+}
+
 template <int K, typename T>
 struct MfmaShape {
     // K = 3: the real embedding (2^(K+1) real rows, re/im interleaved).
@@ -449,7 +462,7 @@ __device__ __forceinline__ void mfma_core_gauss(typename CxT<T>::V* lds, int L, 
             d3[c] = A4{0, 0, 0, 0};
             gcol[c] = gl | gblk;
             gsw[c] = swz(gcol[c]);
-            gin[c] = gsw[c] ^ in_sw;
+            gin[c] = (gsw[c] ^ in_sw) * (uint32_t)sizeof(V);   // byte offsets: one XOR per access
             gblk = ((gblk | ~wmask) + wstep) & wmask;
         });
         // B values (and x + y) one k-step ahead of the MFMAs that use them:
@@ -459,7 +472,7 @@ __device__ __forceinline__ void mfma_core_gauss(typename CxT<T>::V* lds, int L, 
         T bs[2][CH];
         sfor<CH>([&](auto cc) {
             constexpr int c = decltype(cc)::value;
-            bq[0][c] = lds[gin[c]];
+            bq[0][c] = lds_at(lds, gin[c]);
         });
         sfor<CH>([&](auto cc) {
             constexpr int c = decltype(cc)::value;
@@ -473,10 +486,10 @@ __device__ __forceinline__ void mfma_core_gauss(typename CxT<T>::V* lds, int L, 
             constexpr int ks = decltype(kc)::value;
             constexpr int cur = ks & 1;
             if constexpr (ks + 1 < KS) {
-                const uint32_t nx = swz(toff((uint32_t)(4 * (ks + 1))));
+                const uint32_t nx = swz(toff((uint32_t)(4 * (ks + 1)))) * (uint32_t)sizeof(V);
                 sfor<CH>([&](auto cc) {
                     constexpr int c = decltype(cc)::value;
-                    bq[cur ^ 1][c] = lds[gin[c] ^ nx];
+                    bq[cur ^ 1][c] = lds_at(lds, gin[c] ^ nx);
                 });
             }
             __builtin_amdgcn_sched_barrier(0);
@@ -500,13 +513,14 @@ __device__ __forceinline__ void mfma_core_gauss(typename CxT<T>::V* lds, int L, 
         sfor<CH>([&](auto cc) {
             constexpr int c = decltype(cc)::value;
             if (ok[c] && (gcol[c] & op.c_tile) == op.c_tile) {
-                const uint32_t g_out = gsw[c] ^ out_sw;
+                uint32_t g_out = (gsw[c] ^ out_sw) * (uint32_t)sizeof(V);
+                asm volatile("" : "+v"(g_out));   // keeps the byte form (one XOR per store)
                 sfor<4>([&](auto ic) {
                     constexpr int i = decltype(ic)::value;
                     V w;
                     w.x = d1[c][i] - d2[c][i];
                     w.y = d3[c][i] - d1[c][i] - d2[c][i];
-                    lds[g_out ^ swz(toff((uint32_t)i))] = w;
+                    lds_put(lds, g_out ^ (swz(toff((uint32_t)i)) * (uint32_t)sizeof(V)), w);
                 });
             }
         });
@@ -572,14 +586,15 @@ __device__ __forceinline__ void mfma_core(typename CxT<T>::V* lds, int L, const 
             for (int r = 0; r < RPW; ++r) acc[r][c] = A4{0, 0, 0, 0};
             gcol[c] = gl | gblk;
             gsw[c] = swz(gcol[c]);
-            gin[c] = gsw[c] ^ in_sw;
+            // byte offset of this lane's (re or im) value: one XOR per load
+            gin[c] = (gsw[c] ^ in_sw) * (uint32_t)sizeof(V) + part * (uint32_t)sizeof(T);
             gblk = ((gblk | ~wmask) + wstep) & wmask;
         });
         // B values one k-step ahead of the MFMAs that use them
         T bq[2][CH];
         sfor<CH>([&](auto cc) {
             constexpr int c = decltype(cc)::value;
-            bq[0][c] = ldsf[2 * (gin[c] ^ swz(toff(0u))) + part];
+            bq[0][c] = lds_at(ldsf, gin[c] ^ (swz(toff(0u)) * (uint32_t)sizeof(V)));
         });
         // issue priority over the other work-group's waves on this SIMD
         // while the wave streams MFMAs (their tile loads, stores and
@@ -589,10 +604,10 @@ __device__ __forceinline__ void mfma_core(typename CxT<T>::V* lds, int L, const 
             constexpr int ks = decltype(kc)::value;
             constexpr int cur = ks & 1;
             if constexpr (ks + 1 < KS) {
-                const uint32_t nx = swz(toff((uint32_t)(2 * (ks + 1))));
+                const uint32_t nx = swz(toff((uint32_t)(2 * (ks + 1)))) * (uint32_t)sizeof(V);
                 sfor<CH>([&](auto cc) {
                     constexpr int c = decltype(cc)::value;
-                    bq[cur ^ 1][c] = ldsf[2 * (gin[c] ^ nx) + part];
+                    bq[cur ^ 1][c] = lds_at(ldsf, gin[c] ^ nx);
                 });
             }
             // keep the next step's loads ahead of this step's MFMAs (the
@@ -610,18 +625,19 @@ __device__ __forceinline__ void mfma_core(typename CxT<T>::V* lds, int L, const 
         sfor<CH>([&](auto cc) {
             constexpr int c = decltype(cc)::value;
             if (ok[c] && (gcol[c] & op.c_tile) == op.c_tile) {
-                const uint32_t g_out = gsw[c] ^ out_sw;
+                uint32_t g_out = (gsw[c] ^ out_sw) * (uint32_t)sizeof(V);
+                asm volatile("" : "+v"(g_out));   // keeps the byte form (one XOR per store)
 #pragma unroll
                 for (int r = 0; r < RPW; ++r) {
                     const int rb = rg * RPW + r;
-                    const uint32_t o0 = g_out ^ swz(toff((uint32_t)(8 * rb)));
+                    const uint32_t o0 = g_out ^ (swz(toff((uint32_t)(8 * rb))) * (uint32_t)sizeof(V));
                     V w0, w1;
                     w0.x = acc[r][c][0];
                     w0.y = acc[r][c][1];
                     w1.x = acc[r][c][2];
                     w1.y = acc[r][c][3];
-                    lds[o0] = w0;
-                    lds[o0 ^ swz(bit[0])] = w1;
+                    lds_put(lds, o0, w0);
+                    lds_put(lds, o0 ^ (swz(bit[0]) * (uint32_t)sizeof(V)), w1);
                 }
             }
         });
@@ -1000,6 +1016,7 @@ __device__ __forceinline__ uint64_t tile_base(uint64_t tile, const PassHdr* __re
 
 // Amplitudes per thread of the largest LDS tile (2^13 c64, 2^12 c128).
 template <typename T> constexpr int kLdsEpt = sizeof(T) == 4 ? 32 : 16;
+template <typename T> constexpr int kLdsTileBytes = sizeof(T) == 4 ? QOPS_LDS_TILE_BYTES_C64 : QOPS_LDS_TILE_BYTES_C128;
 
 // LDS tile pass, persistent and software-pipelined: a work-group stages the
 // pass's matrix-core fragments and diagonal tables in LDS once, then loops
@@ -1022,7 +1039,9 @@ tile_lds_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict__
 {
     using V = typename CxT<T>::V;
     constexpr int EPT = kLdsEpt<T>;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
+    // one static block at a known LDS address: the swizzled accesses of the
+    // matrix-core loops then take one XOR each and no base add
+    __shared__ __align__(16) unsigned char smem_raw[kLdsTileBytes<T>];
     V* lds = reinterpret_cast<V*>(smem_raw);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -1145,13 +1164,8 @@ static hipError_t launch_tile_lds_f(void* state, const PassHdr* hdr, const DevOp
                                     uint64_t grid, uint64_t ntiles, int lds_bytes, hipStream_t s)
 {
     using V = typename CxT<T>::V;
-    static bool done = false;
-    if (!done) {
-        (void)hipFuncSetAttribute((const void*)tile_lds_kernel<T, HK, FULL>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, tile_max_lds_bytes());
-        done = true;
-    }
-    hipLaunchKernelGGL((tile_lds_kernel<T, HK, FULL>), dim3((unsigned)grid), dim3(256), lds_bytes, s,
+    (void)lds_bytes;   // checked against the kernel's static block by the caller
+    hipLaunchKernelGGL((tile_lds_kernel<T, HK, FULL>), dim3((unsigned)grid), dim3(256), 0, s,
                        reinterpret_cast<V*>(state), hdr, ops, reinterpret_cast<const T*>(coef), ntiles);
     return hipGetLastError();
 }
@@ -1168,8 +1182,11 @@ static hipError_t launch_tile_lds_t(void* state, const PassHdr* hdr, const DevOp
 hipError_t launch_tile_lds(int prec, void* state, const PassHdr* hdr, const DevOp* ops, const void* coef,
                            uint64_t ntiles, int L, int lds_bytes, int grid_cap, int hoist_k, hipStream_t s)
 {
-    // persistent grid: as many work-groups as fit on the chip at this LDS size
-    const int per_cu = std::max(1, std::min(8, tile_max_lds_bytes() / std::max(lds_bytes, 1)));
+    // persistent grid: as many work-groups as fit on the chip (the kernel's
+    // static LDS block; the planner keeps tile plus coefficients within it)
+    const int block = prec == 0 ? QOPS_LDS_TILE_BYTES_C64 : QOPS_LDS_TILE_BYTES_C128;
+    if (lds_bytes > block) return hipErrorInvalidValue;
+    const int per_cu = std::max(1, tile_max_lds_bytes() / block);
     uint64_t grid = std::min<uint64_t>(ntiles, (uint64_t)num_cus() * per_cu);
     if (grid_cap > 0 && grid > (uint64_t)grid_cap) grid = (uint64_t)grid_cap;
     if (grid == 0) grid = 1;

@@ -952,7 +952,7 @@ static int hoist_choice(const Plan& p, int op0, int nops)
 
 // LDS of one work-group of the LDS tile kernel: complex64 passes run two
 // work-groups per CU (the kernel is register-bounded for it), complex128 one
-static size_t lds_budget(int prec) { return prec == 0 ? 80 * 1024 : 160 * 1024; }
+static size_t lds_budget(int prec) { return prec == 0 ? QOPS_LDS_TILE_BYTES_C64 : QOPS_LDS_TILE_BYTES_C128; }
 
 static void emit_tile_lds(Plan& p, PassPlan& pp)
 {
