@@ -194,3 +194,16 @@ def test_wide_blocks_sharing_a_pass(q, prec):
     c = W.Circuit(20, gates)
     got, _ = run_gpu(q, c, prec)
     check_state(got, orc.run_circuit(c), prec, "wide blocks")
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("tile_upper", [4, 5, 6, 7])
+def test_lds_tiles_of_every_width(q, prec, tile_upper):
+    """LDS tile passes of 10..13 bits (6 + tile_upper, at most 13 for
+    complex64 and 12 for complex128): the largest tile runs the branch-free
+    load/store variant, the smaller ones the element-tested one; blocks of
+    2..6 qubits on 16 qubits against the oracle."""
+    c = W.haar_blocks(7, n=16, nblocks=30)
+    ref = orc.run_circuit(c)
+    got, _ = run_gpu(q, c, prec, tile_upper=tile_upper)
+    check_state(got, ref, prec, f"lds tile upper={tile_upper}")
