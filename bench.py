@@ -18,6 +18,7 @@ circuit.
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -279,13 +280,15 @@ def main() -> None:
     passes = plan.passes()
 
     sim = q.Simulator(n, prec)
-    for _ in range(args.warmup):
+    for _ in range(args.warmup):       # the same work as a timed step
         sim.init_basis(circ.x0)
-        sim.run(plan)
+        sim.profile(plan).records()
         sim.expect_z()
     torch.cuda.synchronize()
 
     recs_all = []
+    gc.collect()
+    gc.disable()                       # no collector pauses inside the timed steps
     t0 = time.perf_counter()
     for _ in range(args.steps):
         sim.init_basis(circ.x0)
@@ -295,6 +298,7 @@ def main() -> None:
         z = sim.expect_z()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    gc.enable()
     ms = el / args.steps * 1e3
     norm = sim.norm()
 

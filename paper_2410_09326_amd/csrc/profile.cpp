@@ -73,9 +73,13 @@ int32_t qops_profile_run(qops_sim* h, const qops_plan* plan, qops_profile** out)
         rc = upload_plan(p);
         if (rc) return rc;
         const size_t np = p.passes.size();
-        std::vector<hipEvent_t> ev(np + 1);
-        for (auto& e : ev)
-            if (hipEventCreate(&e) != hipSuccess) return set_error(QOPS_HIP_ERROR, "event create");
+        // events are created once per simulator and reused by later runs
+        while (h->events.size() < np + 1) {
+            hipEvent_t x;
+            if (hipEventCreate(&x) != hipSuccess) return set_error(QOPS_HIP_ERROR, "event create");
+            h->events.push_back(x);
+        }
+        const hipEvent_t* ev = h->events.data();
         hipError_t e = hipEventRecord(ev[0], h->stream);
         for (size_t i = 0; i < np && e == hipSuccess && rc == 0; ++i) {
             rc = launch_pass(h, p, p.passes[i]);
@@ -97,7 +101,6 @@ int32_t qops_profile_run(qops_sim* h, const qops_plan* plan, qops_profile** out)
             pr->total += ms * 1e-3;
             pass_features(p, p.passes[i], &pr->feats[i * kNumFeatures]);
         }
-        for (auto& x : ev) (void)hipEventDestroy(x);
         if (rc) return rc;
         if (e != hipSuccess) return hip_fail(e, "profiling run");
         count_gates(p, pr->lcount, pr->pcount);

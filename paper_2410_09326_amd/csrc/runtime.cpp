@@ -259,6 +259,7 @@ int32_t qops_destroy(qops_sim* h)
     (void)hipStreamSynchronize(h->stream);
     if (h->owned && h->state) (void)hipFree(h->state);
     if (h->scratch) (void)hipFree(h->scratch);
+    for (auto& ev : h->events) (void)hipEventDestroy(ev);
     if (h->last_plan) {
         free_plan_device(*h->last_plan);
         delete h->last_plan;

@@ -20,6 +20,7 @@ struct qops_sim {
     size_t scratch_doubles = 0;
     qops::Plan* last_plan = nullptr;  // kept alive until the next apply / destroy
     int grid_cap = 0;                 // 0 = one work-group per tile
+    std::vector<hipEvent_t> events;   // per-pass timing events of profiled runs (reused)
 };
 
 struct qops_plan {
