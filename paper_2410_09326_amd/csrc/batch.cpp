@@ -72,7 +72,9 @@ int32_t plan_all(qops_batch_exec* e, const qops_batch* b)
         par.state_lds_max_n = e->small_max_n;
         par.max_fuse_k = e->fuse_k;
         par.L_lds = std::min(e->tile_bits, n);
-        // register tiles of the same width: R register bits, the rest wave bits
+        // register tiles of the same width: up to 5 (complex64) / 4
+        // (complex128) register bits, the rest wave bits
+        par.R = b->precision == QOPS_C64 ? 5 : 4;
         par.W = std::max(0, std::min(2, std::min(e->tile_bits, n) - 6 - par.R));
         Err er = build_plan(n, b->precision, nullptr, b->gates[i], b->n_gates[i], par, e->plans[i]);
         if (!er.ok()) return set_error(er.code, "circuit " + std::to_string(i) + ": " + er.msg);

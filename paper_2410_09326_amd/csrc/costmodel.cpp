@@ -121,14 +121,18 @@ int32_t build_priced_plan(int n, int prec, const int32_t* l2p, const qops_gate* 
     }
     const auto t0 = std::chrono::steady_clock::now();
     double best = -1;
-    // candidates: tile width above the six lane bits x qubit remap x block
-    // fusion width (a fixed fusion width in the options is kept)
+    // candidates: tile width above the six lane bits (0 = the default
+    // widths: small register tiles, the largest LDS tile) x qubit remap x
+    // block fusion width (a fixed fusion width in the options is kept)
     const int max_up = prec == QOPS_C64 ? 7 : 6;
     const int k_lo = opts->max_fuse_k > 0 ? opts->max_fuse_k : 1;
     const int k_hi = opts->max_fuse_k > 0 ? opts->max_fuse_k : 4;
+    std::vector<int> widths;
+    if (prec == QOPS_C64) widths.push_back(0);   // for complex128 the default equals width 6
+    for (int up = 4; up <= max_up; ++up) widths.push_back(up);
     for (int kf = k_lo; kf <= k_hi; ++kf)
         for (int remap = 0; remap <= 1; ++remap)
-            for (int up = 4; up <= max_up; ++up) {
+            for (int up : widths) {
                 qops_plan_opts o = *opts;
                 o.tile_upper = up;
                 o.max_fuse_k = kf;
