@@ -264,3 +264,26 @@ def test_rotation_folding_merges_equal_parities():
     assert q.Plan(n, lots.gates).stats()["n_folded"] > 0
     assert q.Plan(n, few.gates).stats()["n_folded"] == 0
     assert q.Plan(n, lots.gates, fold_rotations=-1).stats()["n_folded"] == 0
+
+
+@pytest.mark.parametrize("mode", ["profiled", "learned"])
+def test_priced_plan_is_cheapest_candidate(mode):
+    """Priced planning keeps the cheapest candidate under its own pricing: the
+    chosen plan's predicted time is at most that of the default-width plan
+    and of every explicit tile width (remap on/off, fusion width 1..4)."""
+    import os
+    models = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2410_09326_amd",
+                          "models")
+    if mode == "profiled":
+        kw = {"mode": q.PLAN_PROFILED, "profile": q.Profile.load(os.path.join(models, "corpus_profile.bin"))}
+    else:
+        kw = {"mode": q.PLAN_LEARNED, "model": q.CostModel.load(os.path.join(models, "cost_mlp.bin"))}
+    for seed in (9100, 9101):
+        c = W.eval_circuit(seed, n=24, depth=16)
+        best = q.Plan(c.n, c.gates, precision=q.C64, **kw).stats()["predicted_s"]
+        assert best > 0
+        for tu in (0, 4, 5, 6, 7):
+            for remap in (0, 1):
+                for kf in (1, 2, 3, 4):
+                    cand = q.Plan(c.n, c.gates, precision=q.C64, tile_upper=tu, remap=remap, max_fuse_k=kf)
+                    assert best <= cand.predict(**kw) * (1 + 1e-12), (seed, tu, remap, kf)
