@@ -67,7 +67,7 @@ struct PassHdr {
     int32_t op0;                    // first op in the op array
     uint32_t map0;                  // mapping used for the load
     int32_t nruns;                  // runs of non-tile physical bits
-    int32_t lds_bytes;              // dynamic LDS needed (0 if no LDS op)
+    int32_t lds_bytes;              // LDS the pass needs (0 if no LDS op)
     int32_t coef_src;               // LDS tile pass: coefficients staged into LDS once per
     int32_t coef_n;                 //   work-group: coef[coef_src .. coef_src + coef_n)
     int32_t up_phys[QOPS_MAX_UP];

@@ -19,8 +19,11 @@ int tile_max_lds_bytes();
 hipError_t launch_tile_pass(int prec, int R, int W, void* state, const PassHdr* hdr, const DevOp* ops,
                             const void* coef, uint64_t ntiles, int lds_bytes, int grid_cap, hipStream_t s);
 
-// LDS tile pass (dense blocks): tile of 2^L amplitudes in LDS, 256 threads.
-// hoist_k: qubits of the block whose fragments stay in registers (hdr->hoist), 0 if none.
+// LDS tile pass (dense blocks): tile of 2^L amplitudes in LDS, 256 threads,
+// in one static LDS block per work-group (80 KiB complex64, 160 KiB
+// complex128); `lds_bytes` (tile plus staged coefficients) must fit in it,
+// else hipErrorInvalidValue.  hoist_k: qubits of the block whose fragments
+// stay in registers (hdr->hoist), 0 if none.
 hipError_t launch_tile_lds(int prec, void* state, const PassHdr* hdr, const DevOp* ops, const void* coef,
                            uint64_t ntiles, int L, int lds_bytes, int grid_cap, int hoist_k, hipStream_t s);
 
