@@ -449,6 +449,11 @@ __device__ __forceinline__ void mfma_core_gauss(typename CxT<T>::V* lds, int L, 
         if constexpr (sizeof(T) == 4) return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
         else return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     };
+    // issue priority over the other work-group's waves on this SIMD while
+    // the wave streams MFMAs and writes their results back (the other
+    // work-group's tile loads and stores fill the matrix core's gaps instead
+    // of delaying it)
+    __builtin_amdgcn_s_setprio(1);
     for (int i0 = 0; i0 < nper; i0 += CH) {
         A4 d1[CH], d2[CH], d3[CH];
         uint32_t gsw[CH], gcol[CH], gin[CH];
@@ -478,10 +483,6 @@ __device__ __forceinline__ void mfma_core_gauss(typename CxT<T>::V* lds, int L, 
             constexpr int c = decltype(cc)::value;
             bs[0][c] = bq[0][c].x + bq[0][c].y;
         });
-        // issue priority over the other work-group's waves on this SIMD
-        // while the wave streams MFMAs (their tile loads, stores and
-        // write-backs fill the matrix core's gaps instead of delaying it)
-        __builtin_amdgcn_s_setprio(1);
         sfor<KS>([&](auto kc) {
             constexpr int ks = decltype(kc)::value;
             constexpr int cur = ks & 1;
@@ -508,7 +509,6 @@ __device__ __forceinline__ void mfma_core_gauss(typename CxT<T>::V* lds, int L, 
                 __builtin_amdgcn_sched_barrier(0);
             }
         });
-        __builtin_amdgcn_s_setprio(0);
         if constexpr (RW > 1) __syncthreads();   // the chunk's inputs are read
         sfor<CH>([&](auto cc) {
             constexpr int c = decltype(cc)::value;
@@ -525,6 +525,7 @@ __device__ __forceinline__ void mfma_core_gauss(typename CxT<T>::V* lds, int L, 
             }
         });
     }
+    __builtin_amdgcn_s_setprio(0);
 }
 
 template <int K, typename T>
@@ -571,6 +572,11 @@ __device__ __forceinline__ void mfma_core(typename CxT<T>::V* lds, int L, const 
         if constexpr (sizeof(T) == 4) return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
         else return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     };
+    // issue priority over the other work-group's waves on this SIMD while
+    // the wave streams MFMAs and writes their results back (the other
+    // work-group's tile loads and stores fill the matrix core's gaps instead
+    // of delaying it)
+    __builtin_amdgcn_s_setprio(1);
     for (int i0 = 0; i0 < nper; i0 += CH) {
         A4 acc[RPW][CH];
         uint32_t gsw[CH], gcol[CH], gin[CH];
@@ -596,10 +602,6 @@ __device__ __forceinline__ void mfma_core(typename CxT<T>::V* lds, int L, const 
             constexpr int c = decltype(cc)::value;
             bq[0][c] = lds_at(ldsf, gin[c] ^ (swz(toff(0u)) * (uint32_t)sizeof(V)));
         });
-        // issue priority over the other work-group's waves on this SIMD
-        // while the wave streams MFMAs (their tile loads, stores and
-        // write-backs fill the matrix core's gaps instead of delaying it)
-        __builtin_amdgcn_s_setprio(1);
         sfor<KS>([&](auto kc) {
             constexpr int ks = decltype(kc)::value;
             constexpr int cur = ks & 1;
@@ -620,7 +622,6 @@ __device__ __forceinline__ void mfma_core(typename CxT<T>::V* lds, int L, const 
             });
             __builtin_amdgcn_sched_barrier(0);
         });
-        __builtin_amdgcn_s_setprio(0);
         if constexpr (RW > 1) __syncthreads();   // the chunk's B fragments are read
         sfor<CH>([&](auto cc) {
             constexpr int c = decltype(cc)::value;
@@ -642,6 +643,7 @@ __device__ __forceinline__ void mfma_core(typename CxT<T>::V* lds, int L, const 
             }
         });
     }
+    __builtin_amdgcn_s_setprio(0);
     }
 }
 
