@@ -111,6 +111,15 @@ int32_t qops_create(int32_t n, int32_t precision, void* dev_state, size_t bytes,
                     qops_sim** out);
 /* Frees library-owned memory and plans.  Null is accepted. */
 int32_t qops_destroy(qops_sim* h);
+/* Caps the work-groups of every state pass this handle launches (register
+ * and LDS tile passes, gate-wise sweeps, bit exchanges); 0 (the default)
+ * restores each kernel's own grid: one work-group per tile for register
+ * tiles, as many as fit on the chip for LDS tiles, up to 16384 for sweeps.
+ * The kernels walk the remaining tiles or groups in grid-stride loops, so
+ * the results do not depend on the cap; a small cap makes each work-group
+ * process many tiles (the persistent path a full-size state takes).
+ * QOPS_INVALID_ARG for a negative value. */
+int32_t qops_set_launch_limit(qops_sim* h, int32_t max_workgroups);
 /* Device pointer of the state (physical order) and its size in bytes. */
 int32_t qops_state_pointer(qops_sim* h, void** dev_ptr, size_t* bytes);
 

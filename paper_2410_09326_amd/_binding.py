@@ -98,6 +98,7 @@ SIGNATURES = {
     "qops_version": (_I32, []),
     "qops_create": (_I32, [_I32, _I32, _VP, _SZ, _VP, ctypes.POINTER(_VP)]),
     "qops_destroy": (_I32, [_VP]),
+    "qops_set_launch_limit": (_I32, [_VP, _I32]),
     "qops_state_pointer": (_I32, [_VP, ctypes.POINTER(_VP), ctypes.POINTER(_SZ)]),
     "qops_init_basis": (_I32, [_VP, _U64]),
     "qops_init_amplitudes": (_I32, [_VP, _VP]),
@@ -604,6 +605,10 @@ class Simulator:
             self.close()
         except Exception:
             pass
+
+    def set_launch_limit(self, max_workgroups: int) -> None:
+        """Caps the work-groups of every state pass (0 = the kernels' own)."""
+        check(lib().qops_set_launch_limit(self.handle, int(max_workgroups)))
 
     def init_basis(self, x: int = 0) -> None:
         check(lib().qops_init_basis(self.handle, int(x)))

@@ -1319,17 +1319,18 @@ sweep_diag_kernel(typename CxT<T>::V* __restrict__ st, uint64_t N, int m, int4 p
     }
 }
 
-static unsigned grid_for(uint64_t work, unsigned block)
+static unsigned grid_for(uint64_t work, unsigned block, int grid_cap = 0)
 {
     uint64_t g = (work + block - 1) / block;
     const uint64_t cap = 256ull * 64;   // enough waves to fill 256 CUs, grid-stride beyond
     if (g > cap) g = cap;
+    if (grid_cap > 0 && g > (uint64_t)grid_cap) g = (uint64_t)grid_cap;
     if (g == 0) g = 1;
     return (unsigned)g;
 }
 
 template <typename T>
-static hipError_t launch_sweep_t(void* state, int n, const DevOp* op, const void* coef, hipStream_t s)
+static hipError_t launch_sweep_t(void* state, int n, const DevOp* op, const void* coef, int grid_cap, hipStream_t s)
 {
     using V = typename CxT<T>::V;
     V* st = reinterpret_cast<V*>(state);
@@ -1338,7 +1339,8 @@ static hipError_t launch_sweep_t(void* state, int n, const DevOp* op, const void
     const int2 p45 = make_int2(op->pos[4], op->pos[5]);
     if (op->type == OP_DIAG_LDS) {
         const uint64_t N = 1ull << n;
-        hipLaunchKernelGGL(sweep_diag_kernel<T>, dim3(grid_for(N, 256)), dim3(256), 0, s, st, N, op->a, p03, p45, c);
+        hipLaunchKernelGGL(sweep_diag_kernel<T>, dim3(grid_for(N, 256, grid_cap)), dim3(256), 0, s, st, N, op->a, p03, p45,
+                           c);
         return hipGetLastError();
     }
     const int k = op->a;
@@ -1346,7 +1348,7 @@ static hipError_t launch_sweep_t(void* state, int n, const DevOp* op, const void
     for (int j = 0; j < k; ++j) tmask |= 1ull << op->pos[j];
     const uint64_t cmask = op->c_glob;
     const uint64_t ng = 1ull << (n - k);
-    const dim3 grid(grid_for(ng, 256)), blk(256);
+    const dim3 grid(grid_for(ng, 256, grid_cap)), blk(256);
     switch (k) {
     case 1: hipLaunchKernelGGL((sweep_dense_kernel<T, 1>), grid, blk, 0, s, st, ng, tmask, cmask, p03, p45, c); break;
     case 2: hipLaunchKernelGGL((sweep_dense_kernel<T, 2>), grid, blk, 0, s, st, ng, tmask, cmask, p03, p45, c); break;
@@ -1359,10 +1361,11 @@ static hipError_t launch_sweep_t(void* state, int n, const DevOp* op, const void
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(int prec, void* state, int n, const DevOp* op_host, const void* coef_dev, hipStream_t s)
+hipError_t launch_sweep(int prec, void* state, int n, const DevOp* op_host, const void* coef_dev, int grid_cap,
+                        hipStream_t s)
 {
-    return prec == 0 ? launch_sweep_t<float>(state, n, op_host, coef_dev, s)
-                     : launch_sweep_t<double>(state, n, op_host, coef_dev, s);
+    return prec == 0 ? launch_sweep_t<float>(state, n, op_host, coef_dev, grid_cap, s)
+                     : launch_sweep_t<double>(state, n, op_host, coef_dev, grid_cap, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1383,15 +1386,15 @@ swap_bits_kernel(typename CxT<T>::V* __restrict__ st, uint64_t ng, uint64_t mask
     }
 }
 
-hipError_t launch_swap_bits(int prec, void* state, int n, int a, int b, hipStream_t s)
+hipError_t launch_swap_bits(int prec, void* state, int n, int a, int b, int grid_cap, hipStream_t s)
 {
     const uint64_t ng = 1ull << (n - 2);
     const uint64_t ma = 1ull << a, mb = 1ull << b;
     if (prec == 0)
-        hipLaunchKernelGGL(swap_bits_kernel<float>, dim3(grid_for(ng, 256)), dim3(256), 0, s,
+        hipLaunchKernelGGL(swap_bits_kernel<float>, dim3(grid_for(ng, 256, grid_cap)), dim3(256), 0, s,
                            reinterpret_cast<float2*>(state), ng, ma | mb, ma, mb);
     else
-        hipLaunchKernelGGL(swap_bits_kernel<double>, dim3(grid_for(ng, 256)), dim3(256), 0, s,
+        hipLaunchKernelGGL(swap_bits_kernel<double>, dim3(grid_for(ng, 256, grid_cap)), dim3(256), 0, s,
                            reinterpret_cast<double2*>(state), ng, ma | mb, ma, mb);
     return hipGetLastError();
 }
@@ -1445,8 +1448,9 @@ __device__ __forceinline__ double block_sum_256(double v, double* sh)
 }
 
 // Block b sums the chunk [b 2^s, (b+1) 2^s): part[b*(n+1) + 0] = sum p,
-// part[b*(n+1) + 1 + q] = sum p * bit_q(x).
-template <typename T>
+// part[b*(n+1) + 1 + q] = sum p * bit_q(x).  Bits 8..s-1 of x come from the
+// loop counter; LB >= s - 8 of them are tracked in registers.
+template <typename T, int LB>
 __global__ void __launch_bounds__(256)
 zsum_part_kernel(const typename CxT<T>::V* __restrict__ st, int n, int s, double* __restrict__ part)
 {
@@ -1456,16 +1460,16 @@ zsum_part_kernel(const typename CxT<T>::V* __restrict__ st, int n, int s, double
     const int t = threadIdx.x;
     const int jb = s > 8 ? s - 8 : 0;           // bits 8..s-1 come from the loop counter
     double tot = 0.0;
-    double sb[8];
+    double sb[LB];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) sb[q] = 0.0;
+    for (int q = 0; q < LB; ++q) sb[q] = 0.0;
     for (uint32_t j = 0; (j << 8) < chunk; ++j) {
         const uint32_t off = (j << 8) + t;
         if (off >= chunk) break;
         const double p = prob(st[base + off]);
         tot += p;
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
+        for (int q = 0; q < LB; ++q)
             if (q < jb && ((j >> q) & 1u)) sb[q] += p;
     }
     double* out = part + (uint64_t)blockIdx.x * (n + 1);
@@ -1478,7 +1482,7 @@ zsum_part_kernel(const typename CxT<T>::V* __restrict__ st, int n, int s, double
         else if (q < s) {
             double mine = 0.0;
 #pragma unroll
-            for (int r = 0; r < 8; ++r)
+            for (int r = 0; r < LB; ++r)
                 if (r == q - 8) mine = sb[r];
             v = block_sum_256(mine, sh);
         }
@@ -1508,18 +1512,30 @@ size_t zsum_scratch_doubles(int n)
     return (size_t(1) << (n - s)) * (n + 1);
 }
 
+template <typename T>
+static void launch_zsum_part(const void* state, int n, int s, double* part, hipStream_t st)
+{
+    using V = typename CxT<T>::V;
+    const unsigned nb = 1u << (n - s);
+    if (s <= 16)
+        hipLaunchKernelGGL((zsum_part_kernel<T, 8>), dim3(nb), dim3(256), 0, st, reinterpret_cast<const V*>(state), n,
+                           s, part);
+    else
+        hipLaunchKernelGGL((zsum_part_kernel<T, 16>), dim3(nb), dim3(256), 0, st, reinterpret_cast<const V*>(state),
+                           n, s, part);
+}
+
+static hipError_t launch_zsum_s(int prec, const void* state, int n, int s, double* part, double* out, hipStream_t st)
+{
+    if (prec == 0) launch_zsum_part<float>(state, n, s, part, st);
+    else launch_zsum_part<double>(state, n, s, part, st);
+    hipLaunchKernelGGL(zsum_final_kernel, dim3(n + 1), dim3(256), 0, st, part, (int)(1u << (n - s)), n, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_zsum(int prec, const void* state, int n, double* scratch, double* out, hipStream_t st)
 {
-    const int s = zsum_chunk_bits(n);
-    const unsigned nb = 1u << (n - s);
-    if (prec == 0)
-        hipLaunchKernelGGL(zsum_part_kernel<float>, dim3(nb), dim3(256), 0, st,
-                           reinterpret_cast<const float2*>(state), n, s, scratch);
-    else
-        hipLaunchKernelGGL(zsum_part_kernel<double>, dim3(nb), dim3(256), 0, st,
-                           reinterpret_cast<const double2*>(state), n, s, scratch);
-    hipLaunchKernelGGL(zsum_final_kernel, dim3(n + 1), dim3(256), 0, st, scratch, (int)nb, n, out);
-    return hipGetLastError();
+    return launch_zsum_s(prec, state, n, zsum_chunk_bits(n), scratch, out, st);
 }
 
 // Marginal probabilities.  Three paths:

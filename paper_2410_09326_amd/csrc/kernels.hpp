@@ -32,12 +32,13 @@ hipError_t launch_state_lds(int prec, void* state, int n, const DevOp* ops, int 
                             hipStream_t s);
 
 // Gate-wise HBM sweep of one operation (types OP_DENSE_LDS / OP_DIAG_LDS
-// with physical bit positions; "tile" = whole state).
-hipError_t launch_sweep(int prec, void* state, int n, const DevOp* op_host, const void* coef_dev,
+// with physical bit positions; "tile" = whole state).  grid_cap > 0 limits
+// the work-groups; the kernel walks the rest in a grid-stride loop.
+hipError_t launch_sweep(int prec, void* state, int n, const DevOp* op_host, const void* coef_dev, int grid_cap,
                         hipStream_t s);
 
-// Exchange of physical bits a and b (a != b).
-hipError_t launch_swap_bits(int prec, void* state, int n, int a, int b, hipStream_t s);
+// Exchange of physical bits a and b (a != b); grid_cap as for launch_sweep.
+hipError_t launch_swap_bits(int prec, void* state, int n, int a, int b, int grid_cap, hipStream_t s);
 
 // Writes |x>: zero everywhere, one at x.
 hipError_t launch_init_basis(int prec, void* state, int n, uint64_t x, hipStream_t s);

@@ -1395,7 +1395,23 @@ Err build_plan(int n, int prec, const int32_t* l2p_in, const qops_gate* g, size_
             for (int i = h.op0; i < h.op0 + h.nops; ++i)
                 if (i - h.op0 != h.hoist && !p.dops[i].b)
                     return mkerr(QOPS_UNSUPPORTED, "internal: an LDS-pass operation could not be staged");
+            // the kernel keeps one block of 5 or 6 qubits in registers and
+            // runs the others through the 5-qubit dispatch: a second block as
+            // wide as 6 would be skipped there, so it must never reach it
+            if (h.hoist >= 0) {
+                const int hk = p.dops[h.op0 + h.hoist].a;
+                if (hk != 5 && hk != 6) return mkerr(QOPS_UNSUPPORTED, "internal: hoisted block is not 5 or 6 qubits");
+                for (int i = h.op0; i < h.op0 + h.nops; ++i)
+                    if (i - h.op0 != h.hoist && p.dops[i].type == OP_MFMA && p.dops[i].a > 5)
+                        return mkerr(QOPS_UNSUPPORTED, "internal: two 6-qubit matrix-core blocks in one LDS pass");
+            }
         }
+    for (const PassPlan& pp : p.passes) {
+        if (pp.type != PASS_TILE_LDS && pp.type != PASS_STATE_LDS) continue;
+        for (int i = pp.op0; i < pp.op0 + pp.nops; ++i)
+            if (p.dops[i].type == OP_MFMA && (p.dops[i].a < 3 || p.dops[i].a > 6))
+                return mkerr(QOPS_UNSUPPORTED, "internal: matrix-core block outside 3..6 qubits");
+    }
     p.dirty = true;
     p.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return Err{};

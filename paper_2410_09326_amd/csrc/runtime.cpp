@@ -99,11 +99,11 @@ int32_t launch_pass(qops_sim* h, const Plan& p, const PassPlan& pp)
         e = launch_state_lds(p.prec, h->state, p.n, dops + pp.op0, pp.nops, p.d_coef, h->stream);
         break;
     case PASS_SWEEP:
-        e = launch_sweep(p.prec, h->state, p.n, &p.dops[pp.op0], p.d_coef, h->stream);
+        e = launch_sweep(p.prec, h->state, p.n, &p.dops[pp.op0], p.d_coef, h->grid_cap, h->stream);
         break;
     case PASS_SWAP_BITS:
         e = launch_swap_bits(p.prec, h->state, p.n, std::min(pp.swap_a, pp.swap_b), std::max(pp.swap_a, pp.swap_b),
-                             h->stream);
+                             h->grid_cap, h->stream);
         break;
     }
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
@@ -272,6 +272,14 @@ int32_t qops_destroy(qops_sim* h)
         delete h->last_plan;
     }
     delete h;
+    return QOPS_OK;
+}
+
+int32_t qops_set_launch_limit(qops_sim* h, int32_t max_workgroups)
+{
+    if (!h) return set_error(QOPS_INVALID_ARG, "null handle");
+    if (max_workgroups < 0) return set_error(QOPS_INVALID_ARG, "max_workgroups < 0");
+    h->grid_cap = max_workgroups;
     return QOPS_OK;
 }
 
@@ -465,7 +473,7 @@ int32_t qops_swap(qops_sim* h, int32_t a, int32_t b, int32_t mode)
     }
     if (mode != QOPS_SWAP_PHYSICAL) return set_error(QOPS_INVALID_ARG, "bad swap mode");
     const int pa = h->l2p[a], pb = h->l2p[b];
-    hipError_t e = launch_swap_bits(h->prec, h->state, h->n, std::min(pa, pb), std::max(pa, pb), h->stream);
+    hipError_t e = launch_swap_bits(h->prec, h->state, h->n, std::min(pa, pb), std::max(pa, pb), h->grid_cap, h->stream);
     if (e != hipSuccess) return hip_fail(e, "swap");
     return QOPS_OK;
 }
@@ -495,7 +503,8 @@ int32_t qops_set_layout(qops_sim* h, const int32_t* l2p)
     for (int q = 0; q < n; ++q) {
         const int want = l2p[q], have = cur[q];
         if (want == have) continue;
-        hipError_t e = launch_swap_bits(h->prec, h->state, n, std::min(want, have), std::max(want, have), h->stream);
+        hipError_t e = launch_swap_bits(h->prec, h->state, n, std::min(want, have), std::max(want, have), h->grid_cap,
+                                        h->stream);
         if (e != hipSuccess) return hip_fail(e, "set_layout");
         const int other = p2l[want];
         cur[other] = have;

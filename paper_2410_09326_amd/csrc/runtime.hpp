@@ -19,7 +19,7 @@ struct qops_sim {
     double* scratch = nullptr;        // reductions / readout staging
     size_t scratch_doubles = 0;
     qops::Plan* last_plan = nullptr;  // kept alive until the next apply / destroy
-    int grid_cap = 0;                 // 0 = one work-group per tile
+    int grid_cap = 0;                 // work-group limit of state passes (0 = the kernels' own)
     std::vector<hipEvent_t> events;   // per-pass timing events of profiled runs (reused)
 };
 

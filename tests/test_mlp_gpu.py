@@ -79,6 +79,47 @@ def test_training_reduces_loss_and_predicts(q):
 
 
 @pytest.mark.gpu
+def test_gpu_adam_steps_match_fp64_reference(q):
+    """Full-batch training (batch = rows, so the epoch shuffle only reorders
+    the rows of one sum) for S steps against S FP64 backward + Adam steps of
+    the reference, parameter by parameter.  Adam moves every parameter by
+    about lr per step whatever the gradient's size, so the natural scale of
+    the comparison is the step, S * lr: where FP32 resolves the gradient (at
+    least 1e-3 of the largest of its tensor at every step) the parameters
+    agree to 1e-4 of S * lr, which is a few FP32 units of the parameters
+    themselves; the others (a gradient near zero whose sign FP32 may not
+    resolve) to 1e-2 of S * lr.  A wrong bias correction, beta or moment
+    update moves parameters by O(lr) and fails both bounds."""
+    rows, steps, lr = 64, 4, 1e-3
+    X, t = data(123, rows)
+    p0 = W.mlp_init(21).astype(np.float32)
+    m = q.CostModel(p0)
+    m.train(X, t, epochs=steps, batch=rows, lr=lr, seed=3)
+    got = m.params()[0].astype(np.float64)
+
+    ref = mo.unflatten(p0.astype(np.float64))
+    mom = {k: np.zeros_like(v) for k, v in ref.items()}
+    vel = {k: np.zeros_like(v) for k, v in ref.items()}
+    gmin = {k: np.full(v.shape, np.inf) for k, v in ref.items()}
+    Xd, td = X.astype(np.float64), t.astype(np.float64)
+    for s in range(1, steps + 1):
+        _, g = mo.backward(ref, Xd, td)
+        for k in g:
+            gmin[k] = np.minimum(gmin[k], np.abs(g[k]) / max(float(np.max(np.abs(g[k]))), 1e-300))
+        mo.adam_step(ref, g, mom, vel, s, lr)
+    want = mo.flatten(ref)
+    resolved = mo.flatten(gmin) > 1e-3
+    assert resolved.mean() > 0.8
+    err = np.abs(got - want) / (steps * lr)
+    print(f"adam: max err / (S lr) {err[resolved].max():.2e} resolved, {err.max():.2e} all")
+    assert np.all(err[resolved] <= 1e-4)
+    assert np.all(err <= 1e-2)
+    # the run moved the parameters by Adam's step size, not by lr * gradient
+    moved = np.abs(want - p0.astype(np.float64))[resolved]
+    assert np.median(moved) > 0.5 * lr
+
+
+@pytest.mark.gpu
 def test_learned_model_gains_over_plain_table(q):
     """The shipped network (trained on the GPU from profiling runs) against
     the plain cost table fitted to the shipped profile, on passes of fresh

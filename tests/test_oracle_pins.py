@@ -291,6 +291,96 @@ def test_mlp_gradients_match_finite_differences():
             assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd)), (name, idx, fd, an)
 
 
+def _sparse_params():
+    """Small fixed weights with most entries zero, so that the forward pass
+    can be followed by hand (only the first few units are live)."""
+    p = {k: np.zeros_like(v) for k, v in mlp.init_params(0).items()}
+    p["W1"][0, :2] = [1.0, 1.0]
+    p["W1"][1, :2] = [1.0, -1.0]
+    p["W1"][2, :2] = [0.5, 0.0]
+    p["b1"][:3] = [0.0, 0.5, -2.0]
+    p["W2"][0, :3] = [1.0, 1.0, 1.0]
+    p["W2"][1, :3] = [0.0, -1.0, 0.0]
+    p["b2"][:2] = [0.0, 1.0]
+    p["W3"][0, :2] = [2.0, -3.0]
+    p["b3"][0] = 0.25
+    return p
+
+
+def test_mlp_forward_hand_computed():
+    """Two rows through the 64-128-128-1 perceptron, worked by hand:
+    row a = (2, -1, 0, ...):  z1 = (2-1, 2+1+0.5, 1-2) = (1, 3.5, -1) -> h1 = (1, 3.5, 0)
+                              z2 = (1+3.5+0, -3.5+1) = (4.5, -2.5)     -> h2 = (4.5, 0)
+                              y  = 2*4.5 - 3*0 + 0.25 = 9.25
+    row b = (-1, 3, 0, ...):  z1 = (-1+3, -1-3+0.5, -0.5-2) = (2, -3.5, -2.5) -> h1 = (2, 0, 0)
+                              z2 = (2, 0+1) = (2, 1)                    -> h2 = (2, 1)
+                              y  = 2*2 - 3*1 + 0.25 = 1.25
+    Both ReLUs clip a negative pre-activation that would otherwise reach the
+    output (z1[2] of row a through W2[0, 2]; z2[1] of row a through W3), and
+    every bias enters.  With targets (9, 2) the mean squared error is
+    ((0.25)^2 + (-0.75)^2) / 2 = 0.3125."""
+    p = _sparse_params()
+    X = np.zeros((2, 64))
+    X[0, :2] = [2.0, -1.0]
+    X[1, :2] = [-1.0, 3.0]
+    y, cache = mlp.forward(p, X)
+    assert np.array_equal(y, [9.25, 1.25])
+    assert np.array_equal(cache["h1"][:, :3], [[1.0, 3.5, 0.0], [2.0, 0.0, 0.0]])
+    assert np.array_equal(cache["h2"][:, :2], [[4.5, 0.0], [2.0, 1.0]])
+    assert not cache["h1"][:, 3:].any() and not cache["h2"][:, 2:].any()
+    assert mlp.loss(p, X, [9.0, 2.0]) == 0.3125
+
+
+def test_mlp_backward_hand_computed():
+    """Gradient of the hand-worked case above.  dL/dy = 2 (y - t) / B =
+    (0.25, -0.75); dL/db3 = -0.5; dL/dW3 = 0.25*h2_a + (-0.75)*h2_b =
+    (1.125 - 1.5, -0.75) = (-0.375, -0.75)."""
+    p = _sparse_params()
+    X = np.zeros((2, 64))
+    X[0, :2] = [2.0, -1.0]
+    X[1, :2] = [-1.0, 3.0]
+    _, g = mlp.backward(p, X, [9.0, 2.0])
+    assert g["b3"][0] == -0.5
+    assert np.array_equal(g["W3"][0, :2], [-0.375, -0.75]) and not g["W3"][0, 2:].any()
+    # unit 0 of layer 2 is live for both rows: dL/db2[0] = W3[0] * sum dy = 2 * (-0.5)
+    # unit 1 only for row b: dL/db2[1] = W3[1] * dy_b = -3 * -0.75
+    assert np.array_equal(g["b2"][:2], [-1.0, 2.25])
+
+
+def test_adam_first_step_closed_form():
+    """Kingma & Ba: from zero moments, the bias-corrected first step is
+    lr * g / (|g| + eps) element-wise (bias correction undoes the (1 - beta)
+    factors exactly).  A large eps makes its placement visible: eps added
+    inside the square root, or a missing bias correction, give other values."""
+    g = {"w": np.array([0.5, -2.0, 1e-3, 0.0])}
+    for eps in (1e-8, 0.1):
+        p = {"w": np.array([1.0, 1.0, 1.0, 1.0])}
+        m = {"w": np.zeros(4)}
+        v = {"w": np.zeros(4)}
+        mlp.adam_step(p, g, m, v, 1, 0.1, eps=eps)
+        want = 1.0 - 0.1 * g["w"] / (np.abs(g["w"]) + eps)
+        assert np.max(np.abs(p["w"] - want)) <= 1e-15
+    # eps = 0.1, g = 0.5: 1 - 0.1 * 0.5 / 0.6 exactly
+    assert abs(p["w"][0] - (1.0 - 0.05 / 0.6)) <= 1e-15
+
+
+def test_adam_second_step_hand_computed():
+    """Two steps with gradients 0.5 then -0.25, lr 0.1, betas (0.9, 0.999):
+    m2 = 0.9*0.05 - 0.025 = 0.02, corrected 0.02 / 0.19 = 2/19;
+    v2 = 0.999*0.00025 + 0.001*0.0625 = 0.00031225, corrected
+    0.00031225 / 0.001999 = 312.25 / 1999."""
+    eps = 1e-8
+    p = {"w": np.array([0.0])}
+    m = {"w": np.zeros(1)}
+    v = {"w": np.zeros(1)}
+    mlp.adam_step(p, {"w": np.array([0.5])}, m, v, 1, 0.1, eps=eps)
+    mlp.adam_step(p, {"w": np.array([-0.25])}, m, v, 2, 0.1, eps=eps)
+    assert abs(m["w"][0] - 0.02) <= 1e-17 and abs(v["w"][0] - 0.00031225) <= 1e-18
+    step1 = 0.1 * 0.5 / (0.5 + eps)
+    step2 = 0.1 * (2.0 / 19.0) / (np.sqrt(312.25 / 1999.0) + eps)
+    assert abs(p["w"][0] - (-step1 - step2)) <= 1e-15
+
+
 def test_adam_reduces_loss():
     p = mlp.init_params(1)
     rng = np.random.default_rng(1)
