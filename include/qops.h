@@ -427,6 +427,18 @@ int32_t qops_expect_z(qops_sim* h, double* out);
  * read of the state per eight pairs.  QOPS_QUBIT_RANGE for a qubit outside
  * [0, n).  Blocking. */
 int32_t qops_expect_zz(qops_sim* h, const int32_t* pairs, int32_t npairs, double* out);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * <Z_q> as qops_expect_z, written to DEVICE memory out_dev (n doubles,
+ * logical order, caller-owned), asynchronously on the handle's stream, with
+ * no allocation of any kind.  The partial sums live in one fixed 576 KiB
+ * device array per GPU (held until the process ends) instead of the handle's
+ * growable scratch buffer; every n up to 34 fits it (QOPS_UNSUPPORTED
+ * otherwise).  Every call on a GPU shares that array: calls that overlap in
+ * time on one GPU (other streams, other handles, other threads) race, so
+ * order them on one stream.  The summation order is fixed; for n <= 27 it
+ * is the one qops_expect_z uses. */
+int32_t qops_expect_z_noalloc(qops_sim* h, double* out_dev);
 /* Waits for all work enqueued on the handle's stream. */
 int32_t qops_synchronize(qops_sim* h);
 

@@ -157,6 +157,7 @@ SIGNATURES = {
     "qops_probabilities": (_I32, [_VP, _IP, _I32, _DP]),
     "qops_expect_z": (_I32, [_VP, _DP]),
     "qops_expect_zz": (_I32, [_VP, _IP, _I32, _DP]),
+    "qops_expect_z_noalloc": (_I32, [_VP, _VP]),
     "qops_synchronize": (_I32, [_VP]),
 }
 
@@ -667,6 +668,14 @@ class Simulator:
         out = np.empty(self.n, dtype=np.float64)
         check(lib().qops_expect_z(self.handle, out.ctypes.data_as(_DP)))
         return out
+
+    def expect_z_noalloc(self, out) -> None:
+        """<Z_q> into `out`, a float64 device tensor of n entries, on the
+        handle's stream, without allocating (asynchronous)."""
+        import torch
+        if out.dtype != torch.float64 or not out.is_cuda or out.numel() < self.n or not out.is_contiguous():
+            raise QopsError(-1, "out must be a contiguous float64 device tensor of n entries")
+        check(lib().qops_expect_z_noalloc(self.handle, ctypes.c_void_p(out.data_ptr())))
 
     def expect_zz(self, pairs) -> np.ndarray:
         """<Z_a Z_b> for every pair (a, b) of logical qubits."""

@@ -12,7 +12,8 @@ ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libqops.so")
 OBJ = os.path.join(HERE, "_build")
 
-SOURCES = ["kernels.hip", "mlp.hip", "planner.cpp", "runtime.cpp", "costmodel.cpp", "profile.cpp", "batch.cpp", "readout.hip", "fold.cpp"]
+SOURCES = ["kernels.hip", "mlp.hip", "planner.cpp", "runtime.cpp", "costmodel.cpp", "profile.cpp", "batch.cpp", "readout.hip", "fold.cpp",
+           "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

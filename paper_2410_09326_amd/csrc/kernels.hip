@@ -1538,6 +1538,38 @@ hipError_t launch_zsum(int prec, const void* state, int n, double* scratch, doub
     return launch_zsum_s(prec, state, n, zsum_chunk_bits(n), scratch, out, st);
 }
 
+// Chunks of 2^s amplitudes with s = max(zsum_chunk_bits(n), n - 11): at
+// most 2^11 partial records whatever n is (up to 24 chunk bits at n = 34);
+// for n <= 27 the chunks, and so the summation order, equal launch_zsum's.
+static int zsum_bounded_chunk_bits(int n) { return std::max(zsum_chunk_bits(n), n - 11); }
+
+size_t zsum_bounded_scratch_doubles(int n)
+{
+    return (size_t(1) << (n - zsum_bounded_chunk_bits(n))) * (n + 1) + (n + 1);
+}
+
+// out[q] = sums[0] - 2 sums[1 + l2p[q]]: <Z_q> of logical qubit q.
+__global__ void z_logical_kernel(const double* __restrict__ sums, int n, ZLayout lay, double* __restrict__ out)
+{
+    const int q = threadIdx.x;
+    if (q < n) out[q] = sums[0] - 2.0 * sums[1 + lay.l2p[q]];
+}
+
+hipError_t launch_expect_z_bounded(int prec, const void* state, int n, const int32_t* l2p, double* scratch,
+                                   double* out, hipStream_t st)
+{
+    if (n < 1 || n > QOPS_MAX_QUBITS_DEV) return hipErrorInvalidValue;
+    const int s = zsum_bounded_chunk_bits(n);
+    double* part = scratch;
+    double* sums = scratch + (size_t(1) << (n - s)) * (n + 1);
+    hipError_t e = launch_zsum_s(prec, state, n, s, part, sums, st);
+    if (e != hipSuccess) return e;
+    ZLayout lay;
+    for (int q = 0; q < QOPS_MAX_QUBITS_DEV; ++q) lay.l2p[q] = q < n ? l2p[q] : 0;
+    hipLaunchKernelGGL(z_logical_kernel, dim3(1), dim3(64), 0, st, sums, n, lay, out);
+    return hipGetLastError();
+}
+
 // Marginal probabilities.  Three paths:
 //  (a) m == n: a permutation of |psi|^2, no reduction;
 //  (b) at most 12 marginal bits: block b owns the chunk [b 2^s, (b+1) 2^s),

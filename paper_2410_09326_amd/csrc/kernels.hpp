@@ -48,6 +48,15 @@ hipError_t launch_init_basis(int prec, void* state, int n, uint64_t x, hipStream
 // zsum_scratch_doubles(n) doubles.
 size_t zsum_scratch_doubles(int n);
 hipError_t launch_zsum(int prec, const void* state, int n, double* scratch, double* out, hipStream_t s);
+// <Z_q> of every logical qubit q (l2p: host array of n entries) into out
+// (n doubles, device).  The partial records are bounded: `scratch` must hold
+// zsum_bounded_scratch_doubles(n) doubles, at most 2^11 * 35 + 35 for n <= 34.
+struct ZLayout {
+    int32_t l2p[QOPS_MAX_QUBITS_DEV];
+};
+size_t zsum_bounded_scratch_doubles(int n);
+hipError_t launch_expect_z_bounded(int prec, const void* state, int n, const int32_t* l2p, double* scratch,
+                                   double* out, hipStream_t s);
 
 // Marginal over physical bits pos[0..m-1] (host array); out: 2^m doubles
 // (device).  scratch must hold probs_scratch_doubles(n, m, pos) doubles.

@@ -244,6 +244,7 @@ int32_t qops_create(int32_t n, int32_t precision, void* dev_state, size_t bytes,
         h->prec = precision;
         h->bytes = need;
         h->stream = reinterpret_cast<hipStream_t>(stream);
+        if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
         h->l2p.resize(n);
         for (int q = 0; q < n; ++q) h->l2p[q] = q;
         if (dev_state) {

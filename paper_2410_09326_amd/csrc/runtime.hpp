@@ -15,6 +15,7 @@ struct qops_sim {
     bool owned = false;
     size_t bytes = 0;
     hipStream_t stream = nullptr;
+    int device = 0;                   // HIP device current at creation (owner of the state)
     std::vector<int> l2p;             // logical qubit -> physical bit
     double* scratch = nullptr;        // reductions / readout staging
     size_t scratch_doubles = 0;
