@@ -58,7 +58,8 @@ enum qops_status {
     QOPS_NOT_UNITARY = -8       /* opt-in unitarity check failed             */
 };
 
-/* Thread-local, NUL-terminated description of the last failing call. */
+/* Thread-local, NUL-terminated description of the last failing call.
+ * (Library plumbing; no passage of the paper.) */
 const char* qops_last_error(void);
 /* Library version as 10000*major + 100*minor + patch. */
 int32_t qops_version(void);
@@ -102,14 +103,16 @@ typedef struct qops_gate {
 /* ------------------------------------------------------------ handle ---- */
 typedef struct qops_sim qops_sim;
 
-/* Creates a simulator of n qubits (1 <= n <= 34).  If dev_state is non-null
+/* Paper Sec. II-B: a full-state simulation of n qubits holds all 2^n complex
+ * amplitudes in memory; this handle owns (or borrows) that array on the GPU.
+ * Creates a simulator of n qubits (1 <= n <= 34).  If dev_state is non-null
  * the handle BORROWS that device buffer (bytes >= 2^n * amplitude size; the
  * caller keeps it alive until qops_destroy); otherwise the library allocates
  * and owns it.  `stream` is a hipStream_t (null = default stream).  The state
  * is NOT initialised: call qops_init_basis or qops_init_amplitudes. */
 int32_t qops_create(int32_t n, int32_t precision, void* dev_state, size_t bytes, void* stream,
                     qops_sim** out);
-/* Frees library-owned memory and plans.  Null is accepted. */
+/* Frees library-owned memory and plans.  Null is accepted.  (Plumbing.) */
 int32_t qops_destroy(qops_sim* h);
 /* Caps the work-groups of every state pass this handle launches (register
  * and LDS tile passes, gate-wise sweeps, bit exchanges); 0 (the default)
@@ -120,13 +123,18 @@ int32_t qops_destroy(qops_sim* h);
  * process many tiles (the persistent path a full-size state takes).
  * QOPS_INVALID_ARG for a negative value. */
 int32_t qops_set_launch_limit(qops_sim* h, int32_t max_workgroups);
-/* Device pointer of the state (physical order) and its size in bytes. */
+/* Device pointer of the state (physical order, Sec. III-D: the layout the
+ * virtual swaps leave) and its size in bytes.  The pointer stays owned by
+ * the handle (or by the caller that lent it). */
 int32_t qops_state_pointer(qops_sim* h, void** dev_ptr, size_t* bytes);
 
-/* Sets |x> (x in logical order) and resets the layout to the identity. */
+/* Paper Sec. II-B: the simulation starts from a basis state.  Sets |x> (x in
+ * logical order, x < 2^n, else QOPS_INVALID_ARG) and resets the layout to
+ * the identity.  Asynchronous. */
 int32_t qops_init_basis(qops_sim* h, uint64_t x);
-/* Copies 2^n amplitudes (precision of the handle, logical order) from host
- * memory and resets the layout to the identity.  Blocking. */
+/* Paper Sec. II-B: an arbitrary initial state vector.  Copies 2^n amplitudes
+ * (precision of the handle, logical order; the caller keeps `host`) from
+ * host memory and resets the layout to the identity.  Blocking. */
 int32_t qops_init_amplitudes(qops_sim* h, const void* host);
 
 /* ------------------------------------------------------------- plans ---- */
@@ -174,17 +182,27 @@ typedef struct qops_plan_opts {
                                       gates).  Exact, global phase included.  */
 } qops_plan_opts;
 
-/* Fills opts with the defaults listed above. */
+/* Fills opts with the defaults listed above (Sec. III-D: which optimisations
+ * the optimisation run switches on).  QOPS_INVALID_ARG for null. */
 int32_t qops_plan_opts_default(qops_plan_opts* opts);
 
-/* Builds an execution plan for `gates` on an n-qubit register of the given
- * precision, starting from layout l2p_in (null = identity).  Gates and DENSE
- * matrices are copied; the plan is independent of any handle.  FP64 unitary
- * composition happens here. */
+/* Paper Sec. III-D (the optimisation run): applies the switched-on
+ * optimisations -- virtual swaps, single-qubit gate merging, rotation
+ * folding, profile-guided remapping -- and packs the gates into passes.
+ * Builds an execution plan for `gates` (n_gates entries) on an n-qubit
+ * register of the given precision, starting from layout l2p_in (n entries;
+ * null = identity).  Gates and DENSE matrices are copied; the plan is
+ * independent of any handle and owned by the caller until qops_plan_free.
+ * FP64 unitary composition happens here.  Errors: QOPS_QUBIT_RANGE,
+ * QOPS_DUPLICATE_QUBIT, QOPS_UNSUPPORTED (k > 6, > 4 controls),
+ * QOPS_NOT_UNITARY (opt-in), QOPS_INVALID_ARG (bad mode or pointer). */
 int32_t qops_plan_build(int32_t n, int32_t precision, const int32_t* l2p_in, const qops_gate* gates,
                         size_t n_gates, const qops_plan_opts* opts, qops_plan** out);
+/* Frees a plan and its device image (null accepted). */
 int32_t qops_plan_free(qops_plan* p);
 
+/* Plan statistics: the passes, gates and swaps the optimisations produced
+ * and the planning time (the paper's compile time, Sec. IV-B). */
 typedef struct qops_plan_stats {
     int32_t n_passes;          /* kernel launches over the state              */
     int32_t n_tile_passes;     /* of which fused tile passes                  */
@@ -200,10 +218,13 @@ typedef struct qops_plan_stats {
     int32_t n_folded;          /* phase gates removed by rotation folding     */
 } qops_plan_stats;
 int32_t qops_plan_stats_get(const qops_plan* p, qops_plan_stats* out);
-/* The layout (l2p) the plan leaves behind. */
+/* The layout (l2p, n int32 written to caller memory) the plan leaves
+ * behind: Sec. III-D, virtual swaps relabel where a logical qubit lives. */
 int32_t qops_plan_final_layout(const qops_plan* p, int32_t* l2p);
 
-/* Plan introspection (host only; no GPU needed).  Lowered operations act on
+/* Plan introspection (host only; no GPU needed), the optimisation run's
+ * result of Sec. III-D (merged and virtually swapped gates).  Lowered
+ * operations act on
  * PHYSICAL bits after virtual swaps, single-qubit merging and diagonal
  * fusion.  kind: 0 = one-qubit (2x2 on t[0]), 1 = diagonal table over bits
  * t[0..k-1], 2 = dense 2^k x 2^k on t[0..k-1] (matrix bit order), 3 =
@@ -217,6 +238,8 @@ typedef struct qops_op_info {
     int32_t pass;          /* index of the pass that executes the operation   */
     int32_t n_merged;      /* input gates folded into this operation          */
 } qops_op_info;
+/* Number of lowered operations; operation i (QOPS_INVALID_ARG if i is out
+ * of range). */
 int32_t qops_plan_num_ops(const qops_plan* p, size_t* n);
 int32_t qops_plan_op(const qops_plan* p, size_t i, qops_op_info* info, double* mat);
 
@@ -233,12 +256,16 @@ typedef struct qops_pass_info {
     double bytes_alg;      /* algorithmic HBM bytes                           */
     double flops;          /* algorithmic floating-point operations           */
 } qops_pass_info;
+/* Pass i of the plan (QOPS_INVALID_ARG past the last pass). */
 int32_t qops_plan_pass_info(const qops_plan* p, size_t i, qops_pass_info* info);
 
-/* Runs a plan on the handle (n, precision and the handle's current layout
- * must equal the plan's; otherwise QOPS_BAD_STATE).  Asynchronous. */
+/* Paper Sec. II-B: gate-by-gate update of the full state, here pass by pass.
+ * Runs a plan on the handle (n, precision and the handle's current layout
+ * must equal the plan's; otherwise QOPS_BAD_STATE).  The plan stays owned
+ * by the caller and must outlive the queued work.  Asynchronous. */
 int32_t qops_run_plan(qops_sim* h, const qops_plan* p);
-/* Re-binds the angles / dense matrices of a plan to a new gate list with the
+/* Paper Sec. IV-E (repeated runs of one circuit with new parameters).
+ * Re-binds the angles / dense matrices of a plan to a new gate list with the
  * same structure (same kinds, qubits and controls): the planner runs again on
  * the new parameters with the plan's options, so fused blocks are re-composed
  * in FP64 and the pass structure is kept; the device buffers of the plan are
@@ -246,7 +273,9 @@ int32_t qops_run_plan(qops_sim* h, const qops_plan* p);
  * QOPS_BAD_STATE if the structure differs. */
 int32_t qops_plan_update(qops_plan* p, const qops_gate* gates, size_t n_gates);
 
-/* Plans (opts may be null = defaults) and runs a gate list.  Asynchronous. */
+/* Paper Sec. II-B + III-D: plans (opts may be null = defaults) and runs a
+ * gate list on the handle in one call; the plan is kept by the handle until
+ * the next apply or destroy.  Errors as qops_plan_build.  Asynchronous. */
 int32_t qops_apply(qops_sim* h, const qops_gate* gates, size_t n_gates, const qops_plan_opts* opts);
 
 /* --------------------------------------------------------- profiling ---- */
@@ -273,16 +302,21 @@ typedef struct qops_pass_record {
 } qops_pass_record;
 
 int32_t qops_profile_run(qops_sim* h, const qops_plan* p, qops_profile** out);
+/* Sec. III-C context records: number of pass records, and record i. */
 int32_t qops_profile_num_passes(const qops_profile* pr, size_t* n);
 int32_t qops_profile_pass(const qops_profile* pr, size_t i, qops_pass_record* rec);
-/* Gate counters: counts[kind * n + q] for logical qubit q (targets and
- * controls), and the same per physical bit at the time of the gate. */
+/* Sec. III-C counter records: counts[kind * n + q] for logical qubit q
+ * (targets and controls; QOPS_NUM_KINDS * n int32 each, caller memory,
+ * either may be null), and the same per physical bit at the time of the
+ * gate. */
 int32_t qops_profile_counts(const qops_profile* pr, int32_t* logical, int32_t* physical);
-/* Sum of pass times, and the plan's qubit count. */
+/* Sum of pass times (Sec. III-C timestamps), and the plan's qubit count. */
 int32_t qops_profile_total(const qops_profile* pr, double* seconds, int32_t* n);
-/* Cost-model features of every pass (64 floats per pass, pass order). */
+/* Cost-model features of every pass (64 floats per pass, pass order, into
+ * caller memory): what the profile-guided pricing of Sec. III-D reads. */
 int32_t qops_profile_features(const qops_profile* pr, float* out);
-/* Writes the profile (counters, pass records) as JSON. */
+/* Sec. III-C: the profile is dumped to a file (counters, pass records) as
+ * JSON.  QOPS_INVALID_ARG if the file cannot be written. */
 int32_t qops_profile_dump(const qops_profile* pr, const char* path);
 /* Writes the profile as a Chrome trace-event file (the JSON that
  * chrome://tracing and Perfetto open): one complete event per pass on a
@@ -292,8 +326,9 @@ int32_t qops_profile_dump(const qops_profile* pr, const char* path);
  * the paper's performance-debug use, Sec. IV-D). */
 int32_t qops_profile_trace(const qops_profile* pr, const char* path);
 /* Merges the pass records of `src` into `dst` (a cost table built from many
- * profiling runs). */
+ * profiling runs, Sec. III-C); `src` is unchanged. */
 int32_t qops_profile_merge(qops_profile* dst, const qops_profile* src);
+/* Frees a profile (null accepted). */
 int32_t qops_profile_free(qops_profile* pr);
 
 /* ------------------------------------------------------ cost model ---- */
@@ -307,14 +342,18 @@ int32_t qops_profile_free(qops_profile* pr);
  * Training runs on the GPU (forward, backward of the mean squared error,
  * Adam) with fixed summation orders.  Prices candidate plans in LEARNED mode
  * (the choice of which optimisation to switch on, paper Sec. III-D). */
+/* Number of network parameters (W1..b3). */
 int32_t qops_mlp_num_params(size_t* n);
-/* params may be null (all zero) or hold qops_mlp_num_params floats. */
+/* params may be null (all zero) or hold qops_mlp_num_params floats (copied).
+ * The model is owned by the caller until qops_model_free. */
 int32_t qops_mlp_create(const float* params, size_t n, qops_model** out);
+/* Per-feature standardisation (64 means, 64 positive deviations; copied). */
 int32_t qops_mlp_set_normalization(qops_model* m, const float* mu, const float* sd);
-/* Any of the outputs may be null. */
+/* Copies parameters, means and deviations out; any output may be null. */
 int32_t qops_mlp_get_params(const qops_model* m, float* params, float* mu, float* sd);
 /* Loss (1/rows) sum (y - t)^2 and its gradient w.r.t. every parameter, on
- * the GPU (host arrays in and out).  Blocking. */
+ * the GPU (host arrays in and out: X rows x 64, t rows, grads
+ * qops_mlp_num_params floats).  Blocking. */
 int32_t qops_mlp_grad(qops_model* m, const float* X, const float* t, int32_t rows, float* grads, float* loss);
 /* Trains with Adam (beta 0.9/0.999, eps 1e-8) for `epochs` passes over the
  * rows in batches of `batch`, reshuffled each epoch from `seed`.  Blocking. */
@@ -322,21 +361,25 @@ int32_t qops_mlp_train(qops_model* m, const float* X, const float* t, int32_t ro
                        float lr, uint64_t seed, float* final_loss);
 /* out[r] = the network's output for row r (on the GPU).  Blocking. */
 int32_t qops_mlp_predict(qops_model* m, const float* X, int32_t rows, float* out);
+/* Binary save / load of a model (QOPS_INVALID_ARG on an unreadable or
+ * mismatched file); free accepts null. */
 int32_t qops_model_save(const qops_model* m, const char* path);
 int32_t qops_model_load(const char* path, qops_model** out);
 int32_t qops_model_free(qops_model* m);
 
-/* Predicted run time of a plan under the pricing of `opts` (PROFILED: the
+/* Sec. III-D (profile-guided choice of optimisations).
+ * Predicted run time of a plan under the pricing of `opts` (PROFILED: the
  * plain cost table fitted to opts->profile; LEARNED: opts->model). */
 int32_t qops_plan_predict(const qops_plan* p, const qops_plan_opts* opts, double* seconds);
 /* Predicted time of every pass recorded in `pr` (held-out evaluation of a
  * cost model), out: one double per pass. */
 int32_t qops_profile_predict_passes(const qops_profile* pr, const qops_plan_opts* opts, double* out);
 /* Binary save / load of a profile (pass records, features, counters), the
- * corpus a plain cost table is fitted to. */
+ * corpus a plain cost table is fitted to (Sec. III-C dumps).  Load returns a
+ * library-owned profile (qops_profile_free). */
 int32_t qops_profile_save(const qops_profile* pr, const char* path);
 int32_t qops_profile_load(const char* path, qops_profile** out);
-/* An empty profile to merge runs into. */
+/* An empty profile of n qubits to merge runs into. */
 int32_t qops_profile_create(int32_t n, qops_profile** out);
 
 /* --------------------------------------------------- batched runs ---- */
@@ -373,8 +416,10 @@ typedef struct qops_batch_stats {
     int64_t outputs;
     double state_bytes;            /* device memory of the tile-pass states     */
 } qops_batch_stats;
-/* Plans every circuit, lays out the device program, runs the batch once and
- * captures it as a graph.  Gate lists are copied. */
+/* Sec. IV-E: plans every circuit, lays out the device program, runs the
+ * batch once and captures it as a graph.  Gate lists are copied; the
+ * executor is owned by the caller until qops_batch_free.  Errors as
+ * qops_plan_build for any circuit, QOPS_UNSUPPORTED for n outside 1..26. */
 int32_t qops_batch_create(const qops_batch* b, qops_batch_exec** out);
 /* One graph launch (asynchronous). */
 int32_t qops_batch_launch(qops_batch_exec* e);
@@ -386,9 +431,11 @@ int32_t qops_batch_time(qops_batch_exec* e, int32_t reps, double* seconds);
  * fused operations in FP64 and replaces the coefficients the graph reads;
  * QOPS_BAD_STATE if the structure changed. */
 int32_t qops_batch_update(qops_batch_exec* e, const qops_gate* const* gates, const size_t* n_gates);
+/* Shape the executor chose; frees an executor (null accepted). */
 int32_t qops_batch_info(const qops_batch_exec* e, qops_batch_stats* s);
 int32_t qops_batch_free(qops_batch_exec* e);
-/* Autotuner: times the batch for every (small_max_n, tile_bits, max_fuse_k)
+/* Sec. III-D's profile-then-choose idea applied to launch shapes.
+ * Autotuner: times the batch for every (small_max_n, tile_bits, max_fuse_k)
  * candidate and returns the fastest; results are cached in a text file keyed
  * by the batch's precision, size and qubit-count histogram (cache_path
  * nullable).  b's own shape fields are ignored. */
@@ -396,28 +443,37 @@ int32_t qops_batch_autotune(const qops_batch* b, const char* cache_path, int32_t
                             int32_t* best_tile_bits, int32_t* best_fuse_k, double* best_seconds);
 
 /* ------------------------------------------------------------ layout ---- */
-/* SWAP of logical qubits a and b.  VIRTUAL: exchange l2p[a] and l2p[b], move
- * no amplitude.  PHYSICAL: one bit-exchange pass over the state. */
+/* Paper Sec. III-D, virtual swap: a SWAP becomes a relabelling of where the
+ * two logical qubits live.  SWAP of logical qubits a and b.  VIRTUAL:
+ * exchange l2p[a] and l2p[b], move no amplitude.  PHYSICAL: one
+ * bit-exchange pass over the state (asynchronous).  QOPS_QUBIT_RANGE,
+ * QOPS_DUPLICATE_QUBIT (a == b), QOPS_INVALID_ARG (bad mode). */
 int32_t qops_swap(qops_sim* h, int32_t a, int32_t b, int32_t mode);
-/* Copies the logical-to-physical map (n int32). */
+/* Sec. III-D: copies the logical-to-physical map (n int32, caller memory). */
 int32_t qops_get_layout(qops_sim* h, int32_t* l2p);
-/* Moves amplitudes so that logical qubit q lives in physical bit l2p[q]
- * (a permutation of 0..n-1), by bit-exchange passes. */
+/* Sec. II-B / III-D: moving a qubit into the cheap index bits (the chunk
+ * segment).  Moves amplitudes so that logical qubit q lives in physical bit
+ * l2p[q] (a permutation of 0..n-1, else QOPS_INVALID_ARG), by bit-exchange
+ * passes.  Asynchronous. */
 int32_t qops_set_layout(qops_sim* h, const int32_t* l2p);
 
 /* ----------------------------------------------------------- readout ---- */
 enum qops_order { QOPS_ORDER_LOGICAL = 0, QOPS_ORDER_PHYSICAL = 1 };
-/* Copies the 2^n amplitudes to host memory (caller-owned, 2^n * amplitude
- * size bytes) in logical or physical order.  Blocking. */
+/* Paper Sec. II-B: full-state simulation exposes the intermediate and final
+ * states.  Copies the 2^n amplitudes to host memory (caller-owned, 2^n *
+ * amplitude size bytes) in logical or physical order.  Blocking. */
 int32_t qops_read_state(qops_sim* h, void* host, int32_t order);
-/* sum_x |psi_x|^2, FP64 accumulation, deterministic order.  Blocking. */
+/* Sec. II-B (the probability distribution sums to one): sum_x |psi_x|^2,
+ * FP64 accumulation, deterministic order.  Blocking. */
 int32_t qops_norm(qops_sim* h, double* out);
-/* Marginal distribution of logical qubits q[0..m-1] (1 <= m <= n):
+/* Paper Sec. II-B: the final probability distribution.
+ * Marginal distribution of logical qubits q[0..m-1] (1 <= m <= n):
  * out[y] (2^m doubles) = sum of |psi_x|^2 over x whose bit q_j equals bit j
  * of y.  FP64, deterministic.  Blocking. */
 int32_t qops_probabilities(qops_sim* h, const int32_t* qubits, int32_t m, double* out);
-/* <Z_q> = sum_x |psi_x|^2 (1 - 2 b_q(x)) for every logical qubit (n
- * doubles).  FP64, deterministic.  Blocking. */
+/* Paper Sec. IV-E: expectation values read out after each run.
+ * <Z_q> = sum_x |psi_x|^2 (1 - 2 b_q(x)) for every logical qubit (n
+ * doubles, caller host memory).  FP64, deterministic.  Blocking. */
 int32_t qops_expect_z(qops_sim* h, double* out);
 /* <Z_a Z_b> = sum_x |psi_x|^2 (-1)^(b_a(x) + b_b(x)) for each pair of logical
  * qubits (a, b) = (pairs[2i], pairs[2i+1]), i < npairs: the correlators a
@@ -439,7 +495,7 @@ int32_t qops_expect_zz(qops_sim* h, const int32_t* pairs, int32_t npairs, double
  * order them on one stream.  The summation order is fixed; for n <= 27 it
  * is the one qops_expect_z uses. */
 int32_t qops_expect_z_noalloc(qops_sim* h, double* out_dev);
-/* Waits for all work enqueued on the handle's stream. */
+/* Waits for all work enqueued on the handle's stream.  (Plumbing.) */
 int32_t qops_synchronize(qops_sim* h);
 
 #ifdef __cplusplus
