@@ -9,11 +9,15 @@ then the FP64 <Z_i> reduction.  The plan is
 built once before the timed region (its host time is reported as plan_s).
 
 Prints ONE JSON line.  `value` is the step's algorithmic HBM throughput
-(sum over passes of 2 * 2^n * 8 bytes, plus the 2^n * 8 bytes the reduction
-reads, divided by the step time).  The roofline object describes the kernel
-that takes most of the step, timed live with HIP events on the simulator's
-stream; the CPU baseline is the FP64 oracle on a bounded sample of the same
-circuit.
+(sum over passes of 2 * 2^n * 8 bytes, plus the 2^n * 8 bytes the
+initialisation writes and the reduction reads, divided by the step time) of
+plain (unprofiled) steps.  The same number of profiling-run steps follows:
+HIP events around every pass on the simulator's stream give each kernel's
+average launch time for the roofline object, and the two step times give
+the profiling overhead.  The headline result is compared with a complex128
+run of the same circuit (fidelity, max-abs error).  The CPU baseline is the
+FP64 oracle on a bounded sample of the same circuit; `oracle_timing` times
+the oracle per workload at one thread and at all host threads.
 """
 from __future__ import annotations
 
@@ -243,6 +247,234 @@ def qaoa_sweep(n: int = 28, layers: int = 3, evals: int = 16):
             "total_weight": round(float(np.sum(w)), 6)}
 
 
+def _compare_states(torch, a, b, chunk: int = 1 << 26):
+    """Max-abs error, max |b|, fidelity |<b|a>|^2 and relative norm of two
+    device states in logical order (a: complex64 or complex128, b: the
+    complex128 reference), chunk by chunk on the GPU in FP64."""
+    err, amax, ov, nb = 0.0, 0.0, 0.0 + 0.0j, 0.0
+    for o in range(0, b.numel(), chunk):
+        x = a[o:o + chunk].to(torch.complex128)
+        y = b[o:o + chunk]
+        err = max(err, float((x - y).abs().max()))
+        amax = max(amax, float(y.abs().max()))
+        ov += complex(torch.vdot(y, x).item())
+        nb += float((y.abs() ** 2).sum())
+    return err, amax, abs(ov) ** 2 / nb
+
+
+def headline_accuracy(q, torch, sim, plan, circ, prec):
+    """The headline result against the same circuit in complex128 on the GPU
+    (both end in the same layout; the 30-qubit FP64 oracle is checked on a
+    prefix of this circuit by the full-size tests).  Also times the complex128
+    run."""
+    import numpy as np
+    n = circ.n
+    sim.init_basis(circ.x0)
+    sim.run(plan)
+    l2p = sim.layout()
+    ref = q.Simulator(n, q.C128)
+    plan128 = q.Plan(n, circ.gates, precision=q.C128)
+    ref.init_basis(circ.x0)
+    ref.run(plan128)
+    ref.synchronize()
+    t0 = time.perf_counter()
+    ref.init_basis(circ.x0)
+    ref.run(plan128)
+    ref.synchronize()
+    t128 = time.perf_counter() - t0
+    assert np.array_equal(ref.layout(), l2p)
+    a = sim.buffer.view(torch.complex64 if prec == q.C64 else torch.complex128)
+    b = ref.buffer.view(torch.complex128)
+    err, amax, fid = _compare_states(torch, a, b)   # same physical layout on both sides
+    ref.close()
+    torch.cuda.empty_cache()
+    return {"reference": "complex128 run of the same circuit on the GPU", "max_abs": err,
+            "max_abs_over_max_amp": err / amax, "one_minus_fidelity": max(0.0, 1.0 - fid),
+            "c128_ms": round(t128 * 1e3, 2), "c128_passes": plan128.stats()["n_passes"]}
+
+
+def swap_modes(reps: int = 3):
+    """The 28-qubit QFT of a seeded basis state + 40 random U3/CZ layers with
+    its SWAP network handled physically (bit-exchange passes) and virtually
+    (layout relabelling), in complex64 and complex128: best-of-`reps` circuit
+    wall times, T_phys / T_virt, and the complex64 results against the
+    complex128 ones (fidelity, max-abs).  Context (other hardware, a CPU
+    storage-based simulator): the paper reports 1.10x at 28 qubits."""
+    import numpy as np
+    import torch
+    import paper_2410_09326_amd as q
+    from workloads import circuits as W
+    c = W.qft_then_layers(1, n=28, layers=40)
+    n = c.n
+    res = {"workload": "28-qubit QFT of a seeded basis state (28 H, 378 CP, 14 SWAP) + 40 U3/CZ layers (seed 1)"}
+    states, layouts = {}, {}
+    for prec, tag in ((q.C64, "c64"), (q.C128, "c128")):
+        for mode, mname in ((q.SWAP_PHYSICAL, "physical"), (q.SWAP_VIRTUAL, "virtual")):
+            plan = q.Plan(n, c.gates, precision=prec, swap_mode=mode)
+            sim = q.Simulator(n, prec)
+            best = None
+            for _ in range(reps + 1):
+                sim.init_basis(c.x0)
+                sim.synchronize()
+                t0 = time.perf_counter()
+                sim.run(plan)
+                sim.synchronize()
+                el = time.perf_counter() - t0
+                best = el if best is None else min(best, el)
+            st = plan.stats()
+            res[f"{tag}_{mname}_ms"] = round(best * 1e3, 3)
+            res[f"{tag}_{mname}_passes"] = st["n_passes"]
+            if mname == "virtual":
+                res[f"{tag}_virtual_swaps"] = st["n_virtual_swaps"]
+            if mname == "physical":
+                res[f"{tag}_permute_passes"] = st["n_permute_passes"]
+            # c64 and c128 plans of one mode end in the same layout, so the
+            # two are compared in physical order
+            layouts[(tag, mname)] = sim.layout()
+            buf = sim.buffer.view(torch.complex64 if prec == q.C64 else torch.complex128)
+            states[(tag, mname)] = buf.clone()
+            sim.close()
+            del buf
+            torch.cuda.empty_cache()
+        res[f"{tag}_phys_over_virt"] = round(res[f"{tag}_physical_ms"] / res[f"{tag}_virtual_ms"], 4)
+    for mname in ("physical", "virtual"):
+        assert np.array_equal(layouts[("c64", mname)], layouts[("c128", mname)])
+        err, amax, fid = _compare_states(torch, states[("c64", mname)], states[("c128", mname)])
+        res[f"c64_{mname}_vs_c128"] = {"max_abs": err, "max_abs_over_max_amp": err / amax,
+                                       "one_minus_fidelity": max(0.0, 1.0 - fid)}
+    res["virtual_final_layout_is_reversal"] = bool(np.array_equal(layouts[("c64", "virtual")], np.arange(n)[::-1]))
+    states.clear()
+    torch.cuda.empty_cache()
+    res["paper_context"] = "1.10x at 28 qubits (QFT, CPU + SSD storage-based simulator; Table V)"
+    return res
+
+
+def _host_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    mem = None
+    try:
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemTotal"):
+                    mem = round(int(line.split()[1]) / 2 ** 20, 1)
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": avail, "os_cpu_count": os.cpu_count(), "mem_gib": mem}
+
+
+def _oracle_rate(orc, circ, n_eval: int, max_gates: int, budget_s: float):
+    """Runs the oracle on the first gates of `circ` whose qubits all lie
+    below n_eval (all of them when n_eval = circ.n), on an n_eval-qubit
+    state, until `budget_s` elapse or `max_gates` are done; returns (gates
+    done, seconds, amplitude-gate updates per second)."""
+    import numpy as np
+    psi = np.zeros(2 ** n_eval, dtype=np.complex128)
+    psi[0] = 1.0
+    done, t0 = 0, time.perf_counter()
+    for g in circ.gates[:max_gates]:
+        qs = tuple(g.qubits)
+        if max(qs) >= n_eval or g.controls:
+            continue
+        u = orc.gate_matrix(g.kind, g.params, dense=g.matrix)
+        orc.apply_matrix_inplace(n_eval, psi, u, qs)
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    el = time.perf_counter() - t0
+    return done, el, done * (2 ** n_eval) / el
+
+
+def oracle_timing(out, cb=None):
+    """The FP64 oracle per workload, at one thread and at all host threads,
+    next to the GPU's time for the same workload:
+    * 12-qubit layered U3/CNOT circuit with SWAPs (complex128): in full;
+    * 28-qubit QFT + layers and the 30-qubit Haar-block benchmark: per-gate
+      rates on samples (all threads: the first gates at full size; one
+      thread: the same gate sequence on 22 qubits, where the state is 64 MiB),
+      extrapolated to the whole circuit at full size by amplitude count.  The
+      all-thread sample of the benchmark circuit is the CPU-baseline run
+      `cb` when given."""
+    import numpy as np
+    import torch
+    import paper_2410_09326_amd as q
+    from oracle import oracle as orc
+    from workloads import circuits as W
+    host = _host_info()
+    all_threads = orc.num_threads()
+    res = {"host": host, "threads_all": all_threads}
+    # 12-qubit layered circuit, in full, both thread counts, vs the GPU c128 plan
+    c1 = W.layered_u3_cx(0, n=12, depth=20)
+    rows = {}
+    for t in (1, all_threads):
+        orc.set_num_threads(t)
+        best = None
+        for _ in range(5):
+            t0 = time.perf_counter()
+            orc.run_circuit(c1)
+            el = time.perf_counter() - t0
+            best = el if best is None else min(best, el)
+        rows[t] = best
+    sim = q.Simulator(12, q.C128)
+    plan = q.Plan(12, c1.gates, precision=q.C128)
+    gbest = None
+    for _ in range(10):
+        sim.init_basis(0)
+        sim.synchronize()
+        t0 = time.perf_counter()
+        sim.run(plan)
+        sim.synchronize()
+        el = time.perf_counter() - t0
+        gbest = el if gbest is None else min(gbest, el)
+    sim.close()
+    res["layered12_c128"] = {"gates": len(c1.gates), "oracle_1t_ms": round(rows[1] * 1e3, 3),
+                             "oracle_all_ms": round(rows[all_threads] * 1e3, 3),
+                             "gpu_ms": round(gbest * 1e3, 3), "speedup_vs_all": round(rows[all_threads] / gbest, 1),
+                             "note": "oracle and GPU: whole circuit, best of repeats (GPU: wall time incl. launch)"}
+    # 28-qubit QFT + layers and the 30-qubit benchmark: sampled
+    sw = out.get("swap_modes") or {}
+    for name, circ, gpu_ms in (("qft28", W.qft_then_layers(1, n=28, layers=40), sw.get("c128_virtual_ms")),
+                               ("haar30", W.haar_blocks(2, n=30, nblocks=200),
+                                (out.get("accuracy") or {}).get("c128_ms"))):
+        n = circ.n
+        orc.set_num_threads(all_threads)
+        if name == "haar30" and cb is not None:
+            done_a, el_a = cb["blocks"], cb["seconds"]
+        else:
+            done_a, el_a, _ = _oracle_rate(orc, circ, n, len(circ.gates), 6.0)
+        orc.set_num_threads(1)
+        done_1, el_1, _ = _oracle_rate(orc, circ, 22, len(circ.gates), 4.0)
+        # per-amplitude-gate cost varies with k for dense blocks: scale by the
+        # sample's own mix (sum of 2^k) against the whole circuit's
+        def work(gs, nq):
+            return sum((2 ** len(g.qubits)) * (2 ** nq) for g in gs)
+        whole = work(circ.gates, n)
+        samp_a = work(circ.gates[:done_a], n)
+        est_all = el_a * whole / samp_a
+        g22 = [g for g in circ.gates if max(g.qubits) < 22][:done_1]
+        samp_1 = work(g22, 22)
+        est_1 = el_1 * whole / samp_1
+        res[name] = {"sample_all_threads": f"first {done_a} gates at n={n}, {el_a:.1f} s",
+                     "sample_one_thread": f"first {done_1} gates with all qubits < 22 at n=22, {el_1:.1f} s",
+                     "oracle_all_est_s": round(est_all, 1), "oracle_1t_est_s": round(est_1, 1),
+                     "gpu_c128_ms": gpu_ms,
+                     "speedup_c128_vs_all": round(est_all / (gpu_ms * 1e-3), 1) if gpu_ms else None,
+                     "estimate": "sample time x (whole circuit's sum of 2^k * 2^n) / (sample's)"}
+    orc.set_num_threads(all_threads)
+    return res
+
+
 def main() -> None:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -256,6 +488,9 @@ def main() -> None:
     ap.add_argument("--no-batch-eval", action="store_true")
     ap.add_argument("--no-qaoa-eval", action="store_true")
     ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-swap-eval", action="store_true")
+    ap.add_argument("--no-oracle-timing", action="store_true")
     ap.add_argument("--dump-passes", default="", help="write the last step's pass records (JSON) here")
     ap.add_argument("--trace", default="", help="write the last step's profile as a Chrome trace here")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -282,25 +517,47 @@ def main() -> None:
     sim = q.Simulator(n, prec)
     for _ in range(args.warmup):       # the same work as a timed step
         sim.init_basis(circ.x0)
-        sim.profile(plan).records()
+        sim.run(plan)
         sim.expect_z()
     torch.cuda.synchronize()
 
-    recs_all = []
+    # timed region: plain steps (no per-pass events)
     gc.collect()
     gc.disable()                       # no collector pauses inside the timed steps
     t0 = time.perf_counter()
     for _ in range(args.steps):
         sim.init_basis(circ.x0)
-        prof = sim.profile(plan)          # the plan, with HIP events around every pass
-        recs_all.append(prof.records())
-        last_prof = prof
-        z = sim.expect_z()
+        sim.run(plan)
+        z = sim.expect_z()             # blocking: ends the step
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     gc.enable()
     ms = el / args.steps * 1e3
+
+    # profiled region: the same steps as profiling runs (HIP events around
+    # every pass on the simulator's stream)
+    sim.init_basis(circ.x0)
+    sim.profile(plan).records()
+    sim.expect_z()
+    torch.cuda.synchronize()
+    recs_all = []
+    gc.collect()
+    gc.disable()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sim.init_basis(circ.x0)
+        prof = sim.profile(plan)
+        recs_all.append(prof.records())
+        last_prof = prof
+        sim.expect_z()
+    torch.cuda.synchronize()
+    el_prof = time.perf_counter() - t0
+    gc.enable()
+    ms_prof = el_prof / args.steps * 1e3
     norm = sim.norm()
+    accuracy = None
+    if not args.no_accuracy:
+        accuracy = headline_accuracy(q, torch, sim, plan, circ, prec)
 
     if args.copy_calibration:
         a = torch.empty(2 ** 30, dtype=torch.float64, device="cuda")
@@ -345,6 +602,7 @@ def main() -> None:
     tr = traffic_for(dom, args.workload, bytes_launch)
     roof["traffic"] = tr
     roof["kernel"] = dom
+    roof["timed_over"] = f"{args.steps} profiling-run steps after the timed plain steps (HIP events per pass)"
     roof["launches_per_step"] = d["launches"] // args.steps
     roof["avg_launch_ms"] = round(avg_s * 1e3, 4)
     roof["alg_bytes_per_launch"] = bytes_launch
@@ -369,28 +627,36 @@ def main() -> None:
         "config": {"workload": args.workload, "description": desc, "n_qubits": n, "gates": len(circ.gates),
                    "passes": st["n_passes"], "plan": "fused"},
         "circuit_ms": round(pass_time * 1e3, 3),
+        "profiled_ms_per_step": round(ms_prof, 3),
+        "profiling_overhead": round(ms_prof / ms - 1.0, 4),
         "plan_s": round(plan_s, 4),
         "norm_error": abs(norm - 1.0),
+        "accuracy": accuracy,
         "kernels": {k: {"ms_per_step": round(v["seconds"] / args.steps * 1e3, 3),
                         "launches_per_step": v["launches"] // args.steps} for k, v in per.items()},
         "roofline": roof,
     }
-    if not args.no_learned_eval:
-        sim.close()
+    sim.close()
+    torch.cuda.empty_cache()
+    if not args.no_swap_eval:
+        out["swap_modes"] = swap_modes()
         torch.cuda.empty_cache()
+    if not args.no_learned_eval:
         out["learned_vs_plain"] = learned_vs_plain(args.eval_circuits)
     if not args.no_batch_eval:
         out["batch_sweep"] = batch_sweep(args.batch_reps)
     if not args.no_qaoa_eval:
         out["qaoa_sweep"] = qaoa_sweep()
+    cb = None
     if not args.no_cpu_baseline:
         cb = cpu_baseline(circ, args.cpu_seconds)
         out["cpu_baseline"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in cb.items()
                                if k in ("value", "unit", "cores", "kind", "sample")}
     else:
         out["cpu_baseline"] = None
+    if not args.no_oracle_timing:
+        out["oracle_timing"] = oracle_timing(out, cb if args.workload == "haar30" else None)
     print(json.dumps(out), flush=True)
-    sim.close()
 
 
 if __name__ == "__main__":

@@ -57,6 +57,7 @@ def lib():
                               ctypes.POINTER(ctypes.c_int64)]
         L.orc_basis.argtypes = [ctypes.c_int, dp, ctypes.c_uint64]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
         L.orc_norm.argtypes = [ctypes.c_int, dp]
         L.orc_norm.restype = ctypes.c_double
         L.orc_probabilities.argtypes = [ctypes.c_int, dp, ctypes.c_int, ip, dp]
@@ -173,6 +174,11 @@ def apply_matrix_inplace(n: int, psi: np.ndarray, u: np.ndarray, qubits: Sequenc
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(t: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on (timing only)."""
+    lib().orc_set_num_threads(int(t))
 
 
 def norm(psi: np.ndarray) -> float:

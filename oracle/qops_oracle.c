@@ -222,6 +222,18 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Sets the threads of later OpenMP loops (timing at one thread and at all
+ * host cores); no effect on the arithmetic or its order within a group. */
+void orc_set_num_threads(int t)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
+
 /* |x0>: all zero except amplitude x0 = 1. */
 void orc_basis(int n, double* psi, uint64_t x0)
 {

@@ -13,7 +13,10 @@ properties that hold at any size (the FP64 oracle cannot hold these states):
 * 28-qubit QFT + 40 U3/CZ layers, both swap modes: complex64 against
   complex128 and the inverse circuit returning the seeded basis state;
 * a 32-qubit depth-60 evaluation circuit under the learned and the plain
-  cost-model plans: <Z_i> against the complex128 run.
+  cost-model plans: <Z_i> against the complex128 run;
+* the first blocks of the 30-qubit Haar-block benchmark circuit in the
+  default plan and launch against the FP64 oracle itself, element by
+  element (16 GiB of host memory for the oracle's state).
 """
 import numpy as np
 import pytest
@@ -76,6 +79,36 @@ def test_haar30_c64_against_c128_and_inverse(q):
         assert float(rest.max()) <= tol
     s64.close()
     s128.close()
+
+
+def test_haar30_prefix_against_oracle(q):
+    """The benchmark's own launch path (30 qubits, complex64, default plan:
+    LDS tile passes over 2^17 tiles on the persistent grid, matrix-core
+    blocks, fragments held in registers across tiles) against the FP64
+    oracle on the circuit's first four blocks (k = 6, 6, 3, 3)."""
+    c = W.haar_blocks(2, n=30, nblocks=200)
+    pre = W.Circuit(30, c.gates[:4], x0=c.x0, name="haar30_prefix4")
+    assert [len(g.qubits) for g in pre.gates] == [6, 6, 3, 3]
+    sim = q.Simulator(30, q.C64)
+    sim.init_basis(pre.x0)
+    plan = q.Plan(30, pre.gates, precision=q.C64)
+    assert any(p["type"] == 1 for p in plan.passes())
+    sim.run(plan)
+    assert np.array_equal(sim.layout(), np.arange(30))
+    got = sim.state()
+    sim.close()
+    ref = orc.run_circuit(pre)
+    err, amax, ov = 0.0, 0.0, 0.0 + 0.0j
+    step = 1 << 26
+    for o in range(0, 1 << 30, step):
+        x = got[o:o + step].astype(np.complex128)
+        y = ref[o:o + step]
+        err = max(err, float(np.max(np.abs(x - y))))
+        amax = max(amax, float(np.max(np.abs(y))))
+        ov += np.vdot(y, x)
+    fid = abs(ov) ** 2
+    print(f"haar30 prefix vs oracle: max-abs {err:.3e}, max|psi| {amax:.3e}, 1-F {1 - fid:.3e}")
+    assert err <= 2e-5 and err / amax <= 1e-4 and 1 - fid <= 1e-6
 
 
 @pytest.mark.parametrize("prec", [0, 1])
