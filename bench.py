@@ -159,7 +159,7 @@ def learned_vs_plain(n_circ: int):
             "corpus_passes": summ["passes"], "circuits": detail}
 
 
-def batch_sweep(reps: int):
+def batch_sweep(reps: int, shape=None):
     """The parameter-sweep batch: 512 circuits of 10..22 qubits (RY/RZ layers
     plus a CZ ladder, depth 8..32, seed 5) in complex64, all in one graph
     launch producing <Z_i> for every qubit of every circuit.  The autotuner
@@ -175,7 +175,10 @@ def batch_sweep(reps: int):
     spec = [(c.n, q.GateArray(c.gates)) for c in circs]
     cache = os.path.join(tempfile.gettempdir(), "qops_batch_tune.txt")
     t0 = time.perf_counter()
-    sm, tb, kf, _ = q.Batch.autotune(spec, precision=q.C64, cache=cache)
+    if shape is None:
+        sm, tb, kf, _ = q.Batch.autotune(spec, precision=q.C64, cache=cache)
+    else:
+        sm, tb, kf = shape
     tune_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     b = q.Batch(spec, precision=q.C64, small_max_n=sm, tile_bits=tb, max_fuse_k=kf)
@@ -491,11 +494,22 @@ def main() -> None:
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-swap-eval", action="store_true")
     ap.add_argument("--no-oracle-timing", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline steps (no accuracy check, extra legs or CPU baseline): profiler runs")
+    ap.add_argument("--batch-shape", default="",
+                    help="small_max_n,tile_bits,max_fuse_k for the batch leg instead of autotuning")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="skip the headline steps and every leg but the batch sweep (profiler runs)")
     ap.add_argument("--dump-passes", default="", help="write the last step's pass records (JSON) here")
     ap.add_argument("--trace", default="", help="write the last step's profile as a Chrome trace here")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 2^30 x 8-byte device copy (counter calibration)")
     args = ap.parse_args()
+    if args.headline_only or args.batch_only:
+        args.no_accuracy = args.no_swap_eval = args.no_learned_eval = args.no_qaoa_eval = True
+        args.no_cpu_baseline = args.no_oracle_timing = True
+        args.no_batch_eval = not args.batch_only
+    batch_shape = tuple(int(v) for v in args.batch_shape.split(",")) if args.batch_shape else None
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this simulator has no multi-GPU path (state sharding is a design "
               "note only); run with --gpus 1", file=sys.stderr)
@@ -504,6 +518,10 @@ def main() -> None:
     import numpy as np
     import torch
     import paper_2410_09326_amd as q
+
+    if args.batch_only:
+        print(json.dumps({"batch_sweep": batch_sweep(args.batch_reps, batch_shape)}), flush=True)
+        return
 
     circ, prec, desc = make_workload(args.workload)
     n = circ.n
@@ -644,7 +662,7 @@ def main() -> None:
     if not args.no_learned_eval:
         out["learned_vs_plain"] = learned_vs_plain(args.eval_circuits)
     if not args.no_batch_eval:
-        out["batch_sweep"] = batch_sweep(args.batch_reps)
+        out["batch_sweep"] = batch_sweep(args.batch_reps, batch_shape)
     if not args.no_qaoa_eval:
         out["qaoa_sweep"] = qaoa_sweep()
     cb = None
