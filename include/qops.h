@@ -442,6 +442,77 @@ int32_t qops_batch_free(qops_batch_exec* e);
 int32_t qops_batch_autotune(const qops_batch* b, const char* cache_path, int32_t* best_small_max_n,
                             int32_t* best_tile_bits, int32_t* best_fuse_k, double* best_seconds);
 
+/* -------------------------------------------- host-memory state tier ---- */
+/* Paper Sec. II-B (storage-based simulation: the top index bits, the "file
+ * segment", select a state file; the rest index inside it) and Sec. III-D
+ * (virtual swap keeps the hot qubits out of the file segment).  Here the top
+ * g physical bits select one of 2^g segments of a state kept in pinned host
+ * memory, for states beyond device memory.  A run streams the state through
+ * the device in stages: a stage may hold up to max_active global bits as
+ * device-local bits (its "active" bits), so gates targeting them run; every
+ * other gate's controls and diagonal phases on global bits are resolved per
+ * group of segments.  Profile-guided placement (opts.remap = 1): the gate
+ * counters choose which qubits start in the segment bits (for a basis state
+ * set by qops_tier_init_basis), and when a stage activates a global bit it
+ * exchanges it on the device with the local bit whose qubit is next needed
+ * latest.  The device holds two group slots of 2^(n-g+max_active)
+ * amplitudes; transfers run on two copy streams of the handle, overlapped
+ * with the group plans on the caller's stream. */
+typedef struct qops_tier qops_tier;
+typedef struct qops_tier_opts {
+    int32_t remap;          /* 1 = profile-guided placement and exchanges
+                               (default), 0 = keep the layout               */
+    int32_t reserved;
+    qops_plan_opts plan;    /* options of the per-group plans (mode FUSED or
+                               GATEWISE, fusion width, swap mode); priced
+                               modes fall back to FUSED                      */
+} qops_tier_opts;
+typedef struct qops_tier_stats {
+    int32_t stages;         /* streams of the whole state through the device */
+    int32_t groups;         /* device groups over all stages                 */
+    int32_t exchanges;      /* global<->local bit exchanges inserted         */
+    int32_t virtual_swaps;  /* SWAP gates turned into layout updates         */
+    int32_t gpu_passes;     /* kernel passes over all groups                 */
+    int32_t reserved;
+    double h2d_bytes;       /* host-to-device bytes of the run               */
+    double d2h_bytes;       /* device-to-host bytes of the run               */
+    double seconds;         /* wall time of the run (qops_tier_run)          */
+    double plan_seconds;    /* host time of staging and group planning       */
+} qops_tier_stats;
+/* Fills opts: remap = 1, plan = qops_plan_opts_default. */
+int32_t qops_tier_opts_default(qops_tier_opts* opts);
+/* n qubits (2..34), g = global_bits segment bits (1..min(8, n-1)),
+ * max_active in 1..g.  host_state: caller's PINNED buffer of >= 2^n
+ * amplitudes (kept alive until destroy), or null for a library-owned
+ * hipHostMalloc buffer.  stream: the caller's stream for the group plans.
+ * Errors: QOPS_UNSUPPORTED / QOPS_INVALID_ARG for shapes, QOPS_OUT_OF_MEMORY
+ * or QOPS_HIP_ERROR for allocations.  The state is not initialised. */
+int32_t qops_tier_create(int32_t n, int32_t precision, int32_t global_bits, int32_t max_active, void* host_state,
+                         size_t bytes, void* stream, qops_tier** out);
+int32_t qops_tier_destroy(qops_tier* t);
+/* Host pointer of the state (physical order) and its size in bytes. */
+int32_t qops_tier_state_pointer(qops_tier* t, void** host, size_t* bytes);
+/* |x> in logical order, identity layout.  Blocking (host writes). */
+int32_t qops_tier_init_basis(qops_tier* t, uint64_t x);
+/* Runs a gate list (opts null = defaults); stats may be null.  Blocking.
+ * QOPS_UNSUPPORTED if one gate targets more global bits than max_active. */
+int32_t qops_tier_run(qops_tier* t, const qops_gate* gates, size_t n_gates, const qops_tier_opts* opts,
+                      qops_tier_stats* stats);
+/* Host-only staging of a gate list (no GPU): the stages, groups and
+ * exchanges qops_tier_run would use from layout l2p_in (null = identity, or
+ * with remap the profile-guided placement); l2p_out (nullable, n int32)
+ * receives the final layout.  Byte counts are left 0. */
+int32_t qops_tier_plan(int32_t n, int32_t global_bits, int32_t max_active, const int32_t* l2p_in,
+                       const qops_gate* gates, size_t n_gates, int32_t remap, qops_tier_stats* stats, int32_t* l2p_out);
+/* The layout (n int32): logical qubit q lives in physical bit l2p[q]. */
+int32_t qops_tier_get_layout(qops_tier* t, int32_t* l2p);
+/* <Z_q> of every logical qubit (n doubles), FP64: the segments stream
+ * through the device once.  Blocking. */
+int32_t qops_tier_expect_z(qops_tier* t, double* out);
+/* Copies the state to host memory (2^n amplitudes, caller-owned) in logical
+ * or physical order.  Blocking. */
+int32_t qops_tier_read_state(qops_tier* t, void* host, int32_t order);
+
 /* ------------------------------------------------------------ layout ---- */
 /* Paper Sec. III-D, virtual swap: a SWAP becomes a relabelling of where the
  * two logical qubits live.  SWAP of logical qubits a and b.  VIRTUAL:

@@ -6,4 +6,4 @@ its ctypes binding.  There is no CPU fallback: importing the binding fails if
 the library has not been built."""
 from ._binding import (C64, C128, Batch, ORDER_LOGICAL, ORDER_PHYSICAL, PLAN_FUSED, PLAN_GATEWISE,  # noqa: F401
                        PLAN_LEARNED, PLAN_PROFILED, SWAP_PHYSICAL, SWAP_VIRTUAL, CostModel, GateArray, Plan, Profile, QopsError,
-                       Simulator, lib)
+                       Simulator, TieredSimulator, lib, tier_plan)

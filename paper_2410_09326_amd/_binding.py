@@ -82,6 +82,17 @@ class BatchStats(ctypes.Structure):
                 ("outputs", ctypes.c_int64), ("state_bytes", ctypes.c_double)]
 
 
+class TierOpts(ctypes.Structure):
+    _fields_ = [("remap", ctypes.c_int32), ("reserved", ctypes.c_int32), ("plan", PlanOpts)]
+
+
+class TierStats(ctypes.Structure):
+    _fields_ = [("stages", ctypes.c_int32), ("groups", ctypes.c_int32), ("exchanges", ctypes.c_int32),
+                ("virtual_swaps", ctypes.c_int32), ("gpu_passes", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("h2d_bytes", ctypes.c_double), ("d2h_bytes", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("plan_seconds", ctypes.c_double)]
+
+
 class PassInfo(ctypes.Structure):
     _fields_ = [("type", ctypes.c_int32), ("tile_bits", ctypes.c_int32), ("n_upper", ctypes.c_int32),
                 ("upper", ctypes.c_int32 * 8), ("n_ops", ctypes.c_int32), ("n_remaps", ctypes.c_int32),
@@ -149,6 +160,16 @@ SIGNATURES = {
     "qops_batch_info": (_I32, [_VP, ctypes.POINTER(BatchStats)]),
     "qops_batch_free": (_I32, [_VP]),
     "qops_batch_autotune": (_I32, [ctypes.POINTER(BatchDesc), ctypes.c_char_p, _IP, _IP, _IP, _DP]),
+    "qops_tier_opts_default": (_I32, [ctypes.POINTER(TierOpts)]),
+    "qops_tier_create": (_I32, [_I32, _I32, _I32, _I32, _VP, _SZ, _VP, ctypes.POINTER(_VP)]),
+    "qops_tier_destroy": (_I32, [_VP]),
+    "qops_tier_state_pointer": (_I32, [_VP, ctypes.POINTER(_VP), ctypes.POINTER(_SZ)]),
+    "qops_tier_init_basis": (_I32, [_VP, _U64]),
+    "qops_tier_run": (_I32, [_VP, ctypes.POINTER(Gate), _SZ, ctypes.POINTER(TierOpts), ctypes.POINTER(TierStats)]),
+    "qops_tier_plan": (_I32, [_I32, _I32, _I32, _IP, ctypes.POINTER(Gate), _SZ, _I32, ctypes.POINTER(TierStats), _IP]),
+    "qops_tier_get_layout": (_I32, [_VP, _IP]),
+    "qops_tier_expect_z": (_I32, [_VP, _DP]),
+    "qops_tier_read_state": (_I32, [_VP, _VP, _I32]),
     "qops_swap": (_I32, [_VP, _I32, _I32, _I32]),
     "qops_get_layout": (_I32, [_VP, _IP]),
     "qops_set_layout": (_I32, [_VP, _IP]),
@@ -242,6 +263,10 @@ class GateArray:
 
     def ptr(self):
         return ctypes.cast(self.arr, ctypes.POINTER(Gate))
+
+
+def plan_opts_from(**opts) -> PlanOpts:
+    return plan_opts(**opts)
 
 
 def plan_opts(mode: int = PLAN_FUSED, swap_mode: int = SWAP_VIRTUAL, tile_upper: int = 0, max_fuse_k: int = 0,
@@ -686,3 +711,81 @@ class Simulator:
 
     def synchronize(self) -> None:
         check(lib().qops_synchronize(self.handle))
+
+
+# ---------------------------------------------------------------------------
+# Host-memory state tier
+# ---------------------------------------------------------------------------
+
+def _tier_stats(st: TierStats) -> dict:
+    return {f: getattr(st, f) for f, _ in TierStats._fields_ if f != "reserved"}
+
+
+def tier_plan(n: int, gates, global_bits: int, max_active: int = 1, remap: int = 1,
+              l2p: Optional[Sequence[int]] = None):
+    """Host-only staging of a gate list on a tiered state (no GPU): the
+    stages, groups and exchanges a run would use, and the final layout."""
+    ga = gates if isinstance(gates, GateArray) else GateArray(gates)
+    st = TierStats()
+    out = (ctypes.c_int32 * n)()
+    l2p_arr = (ctypes.c_int32 * n)(*l2p) if l2p is not None else None
+    check(lib().qops_tier_plan(n, global_bits, max_active, l2p_arr, ga.ptr(), ga.n, remap, ctypes.byref(st), out))
+    return _tier_stats(st), np.array(out[:], dtype=np.int32)
+
+
+class TieredSimulator:
+    """A 2^n-amplitude state in pinned host memory whose top `global_bits`
+    physical bits select segments; runs stream it through the device in
+    stages (at most `max_active` segment bits active per device group)."""
+
+    def __init__(self, n: int, precision: int = C64, global_bits: int = 2, max_active: int = 1, stream=None) -> None:
+        import torch
+        self.n = n
+        self.precision = precision
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = ctypes.c_void_p()
+        check(lib().qops_tier_create(n, precision, global_bits, max_active, None, 0,
+                                     ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            lib().qops_tier_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_basis(self, x: int = 0) -> None:
+        check(lib().qops_tier_init_basis(self.handle, int(x)))
+
+    def run(self, gates, remap: int = 1, **plan_opts) -> dict:
+        ga = gates if isinstance(gates, GateArray) else GateArray(gates)
+        o = TierOpts()
+        check(lib().qops_tier_opts_default(ctypes.byref(o)))
+        o.remap = remap
+        o.plan = plan_opts_from(**plan_opts)
+        st = TierStats()
+        check(lib().qops_tier_run(self.handle, ga.ptr(), ga.n, ctypes.byref(o), ctypes.byref(st)))
+        return _tier_stats(st)
+
+    def layout(self) -> np.ndarray:
+        out = (ctypes.c_int32 * self.n)()
+        check(lib().qops_tier_get_layout(self.handle, out))
+        return np.array(out[:], dtype=np.int32)
+
+    def expect_z(self) -> np.ndarray:
+        out = np.empty(self.n, dtype=np.float64)
+        check(lib().qops_tier_expect_z(self.handle, out.ctypes.data_as(_DP)))
+        return out
+
+    def state(self, order: int = ORDER_LOGICAL) -> np.ndarray:
+        dt = np.complex64 if self.precision == C64 else np.complex128
+        out = np.empty(2 ** self.n, dtype=dt)
+        check(lib().qops_tier_read_state(self.handle, out.ctypes.data_as(ctypes.c_void_p), order))
+        return out

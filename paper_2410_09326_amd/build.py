@@ -13,7 +13,7 @@ OUT = os.path.join(HERE, "libqops.so")
 OBJ = os.path.join(HERE, "_build")
 
 SOURCES = ["kernels.hip", "mlp.hip", "planner.cpp", "runtime.cpp", "costmodel.cpp", "profile.cpp", "batch.cpp", "readout.hip", "fold.cpp",
-           "noalloc.hip"]
+           "noalloc.hip", "tier.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

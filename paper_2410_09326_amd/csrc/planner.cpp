@@ -1288,6 +1288,54 @@ static void pack(Plan& p)
     flush();
 }
 
+// Merging, fusion, packing and device-program emission of lowered
+// operations (the back half of build_plan), with the plan's checks.
+static Err finish_plan(Plan& p, std::vector<LOp>& lowered, std::chrono::steady_clock::time_point t0)
+{
+    const PlanParams& par = p.par;
+    if (par.mode == QOPS_PLAN_GATEWISE) {
+        p.lops.swap(lowered);
+    } else {
+        merge_ops(lowered, p.lops);
+        fuse_blocks(p.lops, std::min(par.max_fuse_k, 6));
+    }
+    pack(p);
+    // LDS tile kernels start each of their 256 threads on a distinct tile
+    // element (tiles of at least 2^8); complex64 ones read every coefficient
+    // but the hoisted block's from LDS, so each such op must be staged
+    for (const PassPlan& pp : p.passes)
+        if (pp.type == PASS_TILE_LDS && pp.L < 8)
+            return mkerr(QOPS_UNSUPPORTED, "internal: LDS tile of fewer than 2^8 amplitudes");
+    if (p.prec == 0)
+        for (const PassPlan& pp : p.passes) {
+            if (pp.type != PASS_TILE_LDS) continue;
+            const PassHdr& h = p.hdrs[pp.hdr];
+            for (int i = h.op0; i < h.op0 + h.nops; ++i)
+                if (i - h.op0 != h.hoist && !p.dops[i].b)
+                    return mkerr(QOPS_UNSUPPORTED, "internal: an LDS-pass operation could not be staged");
+            // the kernel keeps one block of 5 or 6 qubits in registers and
+            // runs the others through the 5-qubit dispatch: a second block as
+            // wide as 6 would be skipped there, so it must never reach it
+            if (h.hoist >= 0) {
+                const int hk = p.dops[h.op0 + h.hoist].a;
+                if (hk != 5 && hk != 6) return mkerr(QOPS_UNSUPPORTED, "internal: hoisted block is not 5 or 6 qubits");
+                for (int i = h.op0; i < h.op0 + h.nops; ++i)
+                    if (i - h.op0 != h.hoist && p.dops[i].type == OP_MFMA && p.dops[i].a > 5)
+                        return mkerr(QOPS_UNSUPPORTED, "internal: two 6-qubit matrix-core blocks in one LDS pass");
+            }
+        }
+    for (const PassPlan& pp : p.passes) {
+        if (pp.type != PASS_TILE_LDS && pp.type != PASS_STATE_LDS) continue;
+        for (int i = pp.op0; i < pp.op0 + pp.nops; ++i)
+            if (p.dops[i].type == OP_MFMA && (p.dops[i].a < 3 || p.dops[i].a > 6))
+                return mkerr(QOPS_UNSUPPORTED, "internal: matrix-core block outside 3..6 qubits");
+    }
+    p.dirty = true;
+    p.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return Err{};
+}
+
+
 Err build_plan(int n, int prec, const int32_t* l2p_in, const qops_gate* g, size_t ng, const PlanParams& par, Plan& p)
 {
     const auto t0 = std::chrono::steady_clock::now();
@@ -1375,46 +1423,34 @@ Err build_plan(int n, int prec, const int32_t* l2p_in, const qops_gate* g, size_
     e = lower(n, lg, lng, par.swap_mode, l2p, lowered, p.n_virtual_swaps);
     if (!e.ok()) return e;
     p.l2p_out = l2p;
-    if (par.mode == QOPS_PLAN_GATEWISE) {
-        p.lops.swap(lowered);
-    } else {
-        merge_ops(lowered, p.lops);
-        fuse_blocks(p.lops, std::min(par.max_fuse_k, 6));
+    return finish_plan(p, lowered, t0);
+}
+
+Err plan_from_lops(int n, int prec, std::vector<LOp>& ops, const PlanParams& par, Plan& p)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    if (n < 1 || n > QOPS_MAX_QUBITS) return mkerr(QOPS_UNSUPPORTED, "n must be in [1, 34]");
+    p = Plan();
+    p.n = n;
+    p.prec = prec;
+    p.par = par;
+    if (n < 6 && p.par.mode != QOPS_PLAN_GATEWISE) p.par.state_lds_max_n = std::max(p.par.state_lds_max_n, n);
+    p.l2p_in.resize(n);
+    for (int q = 0; q < n; ++q) p.l2p_in[q] = q;
+    p.l2p_out = p.l2p_in;
+    for (const LOp& o : ops) {
+        const uint64_t bad = n >= 64 ? 0 : ~((1ull << n) - 1);
+        if (o.touch() & bad) return mkerr(QOPS_QUBIT_RANGE, "internal: lowered op outside the state");
     }
-    pack(p);
-    // LDS tile kernels start each of their 256 threads on a distinct tile
-    // element (tiles of at least 2^8); complex64 ones read every coefficient
-    // but the hoisted block's from LDS, so each such op must be staged
-    for (const PassPlan& pp : p.passes)
-        if (pp.type == PASS_TILE_LDS && pp.L < 8)
-            return mkerr(QOPS_UNSUPPORTED, "internal: LDS tile of fewer than 2^8 amplitudes");
-    if (p.prec == 0)
-        for (const PassPlan& pp : p.passes) {
-            if (pp.type != PASS_TILE_LDS) continue;
-            const PassHdr& h = p.hdrs[pp.hdr];
-            for (int i = h.op0; i < h.op0 + h.nops; ++i)
-                if (i - h.op0 != h.hoist && !p.dops[i].b)
-                    return mkerr(QOPS_UNSUPPORTED, "internal: an LDS-pass operation could not be staged");
-            // the kernel keeps one block of 5 or 6 qubits in registers and
-            // runs the others through the 5-qubit dispatch: a second block as
-            // wide as 6 would be skipped there, so it must never reach it
-            if (h.hoist >= 0) {
-                const int hk = p.dops[h.op0 + h.hoist].a;
-                if (hk != 5 && hk != 6) return mkerr(QOPS_UNSUPPORTED, "internal: hoisted block is not 5 or 6 qubits");
-                for (int i = h.op0; i < h.op0 + h.nops; ++i)
-                    if (i - h.op0 != h.hoist && p.dops[i].type == OP_MFMA && p.dops[i].a > 5)
-                        return mkerr(QOPS_UNSUPPORTED, "internal: two 6-qubit matrix-core blocks in one LDS pass");
-            }
-        }
-    for (const PassPlan& pp : p.passes) {
-        if (pp.type != PASS_TILE_LDS && pp.type != PASS_STATE_LDS) continue;
-        for (int i = pp.op0; i < pp.op0 + pp.nops; ++i)
-            if (p.dops[i].type == OP_MFMA && (p.dops[i].a < 3 || p.dops[i].a > 6))
-                return mkerr(QOPS_UNSUPPORTED, "internal: matrix-core block outside 3..6 qubits");
-    }
-    p.dirty = true;
-    p.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    return Err{};
+    return finish_plan(p, ops, t0);
+}
+
+Err lower_gates(int n, const qops_gate* g, size_t ng, int swap_mode, std::vector<int>& l2p, std::vector<LOp>& out,
+                int& nvirt)
+{
+    Err e = validate_gates(n, g, ng, false);
+    if (!e.ok()) return e;
+    return lower(n, g, ng, swap_mode, l2p, out, nvirt);
 }
 
 Err update_plan(Plan& p, const qops_gate* g, size_t ng)

@@ -100,6 +100,13 @@ Err validate_gates(int n, const qops_gate* g, size_t ng, bool check_unitary);
 // packing, device program emission).
 Err build_plan(int n, int prec, const int32_t* l2p_in, const qops_gate* g, size_t ng, const PlanParams& par,
                Plan& out);
+// Lowers gates onto physical bits with the running layout l2p (updated in
+// place; unconditioned SWAPs are layout updates in VIRTUAL mode).
+Err lower_gates(int n, const qops_gate* g, size_t ng, int swap_mode, std::vector<int>& l2p, std::vector<LOp>& out,
+                int& nvirt);
+// Plans already-lowered operations on an n-bit state in identity layout
+// (merging, fusion, packing, device program); `ops` is consumed.
+Err plan_from_lops(int n, int prec, std::vector<LOp>& ops, const PlanParams& par, Plan& p);
 // Rebinds angles/matrices (same structure) and re-emits coefficients.
 Err update_plan(Plan& p, const qops_gate* g, size_t ng);
 
