@@ -596,6 +596,17 @@ int32_t qops_tier_run(qops_tier* t, const qops_gate* gates, size_t n_gates, cons
         TierProgram prog;
         Err e = plan_tier(t->n, t->prec, t->g, t->amax, l2p, gates, n_gates, remap != 0, par, true, prog);
         if (!e.ok()) return set_error(e.code, e.msg);
+        // device images of every group plan before the pipeline starts (the
+        // uploads are synchronous copies)
+        for (TierStage& st : prog.stages)
+            for (TierGroup& gr : st.groups) {
+                int32_t urc = upload_plan(gr.plan);
+                if (urc) {
+                    for (TierStage& s2 : prog.stages)
+                        for (TierGroup& g2 : s2.groups) free_plan_device(g2.plan);
+                    return urc;
+                }
+            }
         const auto t0 = std::chrono::steady_clock::now();
         qops_sim sim;
         sim.prec = t->prec;
