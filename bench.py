@@ -478,6 +478,69 @@ def oracle_timing(out, cb=None):
     return res
 
 
+def host_tier(n: int, g: int = 2, amax: int = 1):
+    """The out-of-core tier: an n-qubit complex64 QFT of a seeded basis state
+    whose top g index bits live in pinned host memory (segments of 2^(n-g)
+    amplitudes), streamed through two device group slots, with the
+    profile-guided placement on and off.  Sampled amplitudes are checked
+    against the QFT's closed form (magnitude 2^(-n/2), phase 2 pi x y / 2^n
+    from the exact integer product).  For n that fits the device, the same
+    circuit is also timed with the state in HBM."""
+    import numpy as np
+    import torch
+    import paper_2410_09326_amd as q
+    from workloads import circuits as W
+    x0 = int(W.rng_for(1).integers(2 ** n))
+    c = W.qft(n, x0)
+    res = {"workload": f"{n}-qubit QFT of a seeded basis state, complex64, top {g} bits in pinned host memory "
+                       f"({2 ** g} segments of {2 ** (n - g) * 8 / 2 ** 30:.2f} GiB), {amax} active segment bit(s) per "
+                       f"device group", "state_gib": 2 ** n * 8 / 2 ** 30}
+    t0 = time.perf_counter()
+    t = q.TieredSimulator(n, q.C64, global_bits=g, max_active=amax)
+    res["create_s"] = round(time.perf_counter() - t0, 2)
+    ys = np.concatenate([np.arange(64, dtype=np.uint64),
+                         np.random.default_rng(11).integers(0, 2 ** n, 1 << 14).astype(np.uint64)])
+    ph = ((np.uint64(x0) * ys) % np.uint64(2 ** n)).astype(np.float64) * (2 * np.pi / 2 ** n)
+    ref = np.exp(1j * ph) * 2.0 ** (-n / 2)
+    for remap in (1, 0):
+        t.init_basis(x0)
+        st = t.run(c.gates, remap=remap)
+        l2p = t.layout()
+        view = t.host_view()
+        phys = np.zeros(ys.size, dtype=np.uint64)
+        for qb in range(n):
+            phys |= ((ys >> np.uint64(qb)) & np.uint64(1)) << np.uint64(int(l2p[qb]))
+        got = view[phys.astype(np.int64)].astype(np.complex128)
+        err = float(np.max(np.abs(got - ref)))
+        tag = "placed" if remap else "identity"
+        res[tag] = {"seconds": round(st["seconds"], 3), "stages": st["stages"], "groups": st["groups"],
+                    "exchanges": st["exchanges"], "gpu_passes": st["gpu_passes"],
+                    "h2d_gb": round(st["h2d_bytes"] / 1e9, 2), "d2h_gb": round(st["d2h_bytes"] / 1e9, 2),
+                    "pcie_gbs_each_way": round(st["h2d_bytes"] / st["seconds"] / 1e9, 1),
+                    "plan_s": round(st["plan_seconds"], 4), "sampled_max_abs": err,
+                    "sampled_max_abs_over_amp": err * 2 ** (n / 2)}
+    t0 = time.perf_counter()
+    z = t.expect_z()
+    res["expect_z_s"] = round(time.perf_counter() - t0, 3)
+    res["max_abs_expect_z"] = float(np.max(np.abs(z)))   # a QFT of a basis state has <Z_q> = 0
+    t.close()
+    free, _ = torch.cuda.mem_get_info()
+    if 2 ** n * 8 * 1.1 < free:
+        sim = q.Simulator(n, q.C64)
+        plan = q.Plan(n, c.gates, precision=q.C64)
+        sim.init_basis(x0)
+        sim.run(plan)
+        sim.synchronize()
+        t0 = time.perf_counter()
+        sim.init_basis(x0)
+        sim.run(plan)
+        sim.synchronize()
+        res["in_hbm_seconds"] = round(time.perf_counter() - t0, 4)
+        sim.close()
+        torch.cuda.empty_cache()
+    return res
+
+
 def main() -> None:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -494,6 +557,10 @@ def main() -> None:
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-swap-eval", action="store_true")
     ap.add_argument("--no-oracle-timing", action="store_true")
+    ap.add_argument("--no-tier-eval", action="store_true")
+    ap.add_argument("--tier-qubits", type=int, default=30,
+                    help="qubits of the host-memory tier leg (34 needs 128 GiB of pinned host memory)")
+    ap.add_argument("--tier-only", action="store_true", help="only the host-memory tier leg")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the headline steps (no accuracy check, extra legs or CPU baseline): profiler runs")
     ap.add_argument("--batch-shape", default="",
@@ -507,7 +574,7 @@ def main() -> None:
     args = ap.parse_args()
     if args.headline_only or args.batch_only:
         args.no_accuracy = args.no_swap_eval = args.no_learned_eval = args.no_qaoa_eval = True
-        args.no_cpu_baseline = args.no_oracle_timing = True
+        args.no_cpu_baseline = args.no_oracle_timing = args.no_tier_eval = True
         args.no_batch_eval = not args.batch_only
     batch_shape = tuple(int(v) for v in args.batch_shape.split(",")) if args.batch_shape else None
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -521,6 +588,9 @@ def main() -> None:
 
     if args.batch_only:
         print(json.dumps({"batch_sweep": batch_sweep(args.batch_reps, batch_shape)}), flush=True)
+        return
+    if args.tier_only:
+        print(json.dumps({"host_tier": host_tier(args.tier_qubits)}), flush=True)
         return
 
     circ, prec, desc = make_workload(args.workload)
@@ -659,6 +729,8 @@ def main() -> None:
     if not args.no_swap_eval:
         out["swap_modes"] = swap_modes()
         torch.cuda.empty_cache()
+    if not args.no_tier_eval:
+        out["host_tier"] = host_tier(args.tier_qubits)
     if not args.no_learned_eval:
         out["learned_vs_plain"] = learned_vs_plain(args.eval_circuits)
     if not args.no_batch_eval:

@@ -789,3 +789,13 @@ class TieredSimulator:
         out = np.empty(2 ** self.n, dtype=dt)
         check(lib().qops_tier_read_state(self.handle, out.ctypes.data_as(ctypes.c_void_p), order))
         return out
+
+    def host_view(self) -> np.ndarray:
+        """The pinned host state itself (physical order, no copy); valid
+        until close()."""
+        p = ctypes.c_void_p()
+        nb = ctypes.c_size_t()
+        check(lib().qops_tier_state_pointer(self.handle, ctypes.byref(p), ctypes.byref(nb)))
+        dt = np.complex64 if self.precision == C64 else np.complex128
+        buf = (ctypes.c_char * nb.value).from_address(p.value)
+        return np.frombuffer(buf, dtype=dt)
