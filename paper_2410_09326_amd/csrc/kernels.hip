@@ -259,8 +259,17 @@ __device__ __forceinline__ void oneq_lane(int t, int lane, V (&a)[1 << R], V m00
 // LDS-resident operations (tile of 2^L amplitudes at `lds`)
 // ---------------------------------------------------------------------------
 
+// Fused multiply-add in the state precision.
+__device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // Dense 2^K x 2^K on tile positions pos[0..K-1] (matrix bit order), vector
-// ALU.  Every thread handles whole groups.
+// ALU.  Every thread handles whole groups.  Group g of the tile has its
+// target bits zero and its other bits taken from g in order; the insertion
+// is GF(2)-linear, as is the LDS swizzle, so the byte offsets of a thread's
+// groups are one XOR of a per-thread part and a per-iteration part.  The
+// coefficients are read once per operation; each complex product-sum is
+// four fused multiply-adds.
 template <int K, typename T>
 __device__ void dense_lds(typename CxT<T>::V* lds, int L, const DevOp& op, const T* __restrict__ U, int tid,
                           int nthr)
@@ -268,6 +277,8 @@ __device__ void dense_lds(typename CxT<T>::V* lds, int L, const DevOp& op, const
     using V = typename CxT<T>::V;
     constexpr int D = 1 << K;
     uint32_t mask = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) mask |= 1u << op.pos[j];
     uint32_t toff[D];
 #pragma unroll
     for (int s = 0; s < D; ++s) {
@@ -275,29 +286,59 @@ __device__ void dense_lds(typename CxT<T>::V* lds, int L, const DevOp& op, const
 #pragma unroll
         for (int j = 0; j < K; ++j)
             if (s & (1 << j)) o |= 1u << op.pos[j];
-        toff[s] = o;
+        toff[s] = swz(o) * (uint32_t)sizeof(V);
     }
+    T ur[D * D], ui[D * D];
+    if constexpr (K <= 2) {
 #pragma unroll
-    for (int j = 0; j < K; ++j) mask |= 1u << op.pos[j];
+        for (int i = 0; i < D * D; ++i) {
+            ur[i] = U[2 * i];
+            ui[i] = U[2 * i + 1];
+        }
+    }
     const uint32_t ngroups = 1u << (L - K);
-    for (uint32_t g = tid; g < ngroups; g += nthr) {
-        const uint32_t gb = spread_mask(g, mask);
+    const uint32_t gt = spread_mask((uint32_t)tid, mask);   // tid < nthr <= ngroups or no group at all
+    const uint32_t tsw = swz(gt) * (uint32_t)sizeof(V);
+    unsigned char* base = reinterpret_cast<unsigned char*>(lds);
+    for (uint32_t g0 = 0; g0 + (uint32_t)tid < ngroups; g0 += (uint32_t)nthr) {
+        const uint32_t gu = spread_mask(g0, mask);          // uniform part
+        const uint32_t gb = gt ^ gu;
         if ((gb & op.c_tile) != op.c_tile) continue;
+        const uint32_t off = tsw ^ (swz(gu) * (uint32_t)sizeof(V));
         V in[D];
 #pragma unroll
-        for (int s = 0; s < D; ++s) in[s] = lds[swz(gb + toff[s])];
+        for (int s = 0; s < D; ++s) in[s] = *reinterpret_cast<const V*>(base + (off ^ toff[s]));
 #pragma unroll
         for (int r = 0; r < D; ++r) {
-            V acc;
-            acc.x = 0;
-            acc.y = 0;
+            T ax, ay;
+            if constexpr (K <= 2) {
+                ax = ur[r * D] * in[0].x;
+                ay = ur[r * D] * in[0].y;
+                ax = fmat(-ui[r * D], in[0].y, ax);
+                ay = fmat(ui[r * D], in[0].x, ay);
 #pragma unroll
-            for (int s = 0; s < D; ++s) {
-                const T ur = U[2 * (r * D + s)], ui = U[2 * (r * D + s) + 1];
-                acc.x += ur * in[s].x - ui * in[s].y;
-                acc.y += ur * in[s].y + ui * in[s].x;
+                for (int c = 1; c < D; ++c) {
+                    ax = fmat(ur[r * D + c], in[c].x, ax);
+                    ax = fmat(-ui[r * D + c], in[c].y, ax);
+                    ay = fmat(ur[r * D + c], in[c].y, ay);
+                    ay = fmat(ui[r * D + c], in[c].x, ay);
+                }
+            } else {
+                ax = 0;
+                ay = 0;
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    const T cr = U[2 * (r * D + c)], ci = U[2 * (r * D + c) + 1];
+                    ax = fmat(cr, in[c].x, ax);
+                    ax = fmat(-ci, in[c].y, ax);
+                    ay = fmat(cr, in[c].y, ay);
+                    ay = fmat(ci, in[c].x, ay);
+                }
             }
-            lds[swz(gb + toff[r])] = acc;
+            V w;
+            w.x = ax;
+            w.y = ay;
+            *reinterpret_cast<V*>(base + (off ^ toff[r])) = w;
         }
     }
 }
