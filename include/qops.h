@@ -369,7 +369,10 @@ int32_t qops_model_free(qops_model* m);
 
 /* Sec. III-D (profile-guided choice of optimisations).
  * Predicted run time of a plan under the pricing of `opts` (PROFILED: the
- * plain cost table fitted to opts->profile; LEARNED: opts->model). */
+ * plain cost table of opts->profile -- per pass shape (kernel kind, tile
+ * width, register/wave split, widest dense block, operation count) the
+ * median measured time per amplitude, falling back to coarser shapes;
+ * LEARNED: opts->model). */
 int32_t qops_plan_predict(const qops_plan* p, const qops_plan_opts* opts, double* seconds);
 /* Predicted time of every pass recorded in `pr` (held-out evaluation of a
  * cost model), out: one double per pass. */
@@ -379,6 +382,12 @@ int32_t qops_profile_predict_passes(const qops_profile* pr, const qops_plan_opts
  * library-owned profile (qops_profile_free). */
 int32_t qops_profile_save(const qops_profile* pr, const char* path);
 int32_t qops_profile_load(const char* path, qops_profile** out);
+/* A compact profile that prices like `src` under the plain table: per pass
+ * shape (kernel kind, tile width, register/wave split, widest dense block,
+ * operation count) it keeps the passes at the 10/30/50/70/90th percentiles of
+ * time per amplitude (all of them for shapes with at most five).  For
+ * shipping a table fitted to a large corpus.  Library-owned result. */
+int32_t qops_profile_compact(const qops_profile* src, qops_profile** out);
 /* An empty profile of n qubits to merge runs into. */
 int32_t qops_profile_create(int32_t n, qops_profile** out);
 

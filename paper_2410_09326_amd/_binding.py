@@ -135,6 +135,7 @@ SIGNATURES = {
     "qops_profile_merge": (_I32, [_VP, _VP]),
     "qops_profile_free": (_I32, [_VP]),
     "qops_profile_create": (_I32, [_I32, ctypes.POINTER(_VP)]),
+    "qops_profile_compact": (_I32, [_VP, ctypes.POINTER(_VP)]),
     "qops_profile_save": (_I32, [_VP, ctypes.c_char_p]),
     "qops_profile_load": (_I32, [ctypes.c_char_p, ctypes.POINTER(_VP)]),
     "qops_profile_predict_passes": (_I32, [_VP, ctypes.POINTER(PlanOpts), _DP]),
@@ -424,6 +425,13 @@ class Profile:
 
     def save(self, path: str) -> None:
         check(lib().qops_profile_save(self.handle, path.encode()))
+
+    def compact(self) -> "Profile":
+        """Per pass shape, the passes at five time percentiles: prices like
+        this profile under the plain table."""
+        h = ctypes.c_void_p()
+        check(lib().qops_profile_compact(self.handle, ctypes.byref(h)))
+        return Profile(h)
 
     @classmethod
     def load(cls, path: str) -> "Profile":

@@ -65,9 +65,8 @@ def collect(n_circuits: int, seed0: int = 1000, time_budget: float = 240.0, max_
         held = (i % 10) == 9
         if held:
             hold_prof = prof if hold_prof is None else (hold_prof.merge(prof) or hold_prof)
-        elif i % 32 == 0:
-            # the plain cost table is fitted to every 32nd training circuit (a
-            # compact profile that ships with the package)
+        else:
+            # every training circuit feeds the plain table as well
             train_prof = prof if train_prof is None else (train_prof.merge(prof) or train_prof)
         feats.append(f)
         logt.append(np.log(t))
@@ -112,14 +111,18 @@ def main() -> None:
     loss = model.train(Xtr, ytr, epochs=args.epochs, batch=256, lr=1e-3, seed=3)
     train_s = time.time() - t0
     model.save(os.path.join(args.out, "cost_mlp.bin"))
-    train_prof.save(os.path.join(args.out, "corpus_profile.bin"))
+    shipped = train_prof.compact()
+    shipped.save(os.path.join(args.out, "corpus_profile.bin"))
     true = np.exp(y[held])
     pred_mlp = hold_prof.predict_passes(mode=q.PLAN_LEARNED, model=model)
-    pred_plain = hold_prof.predict_passes(mode=q.PLAN_PROFILED, profile=train_prof)
+    pred_plain = hold_prof.predict_passes(mode=q.PLAN_PROFILED, profile=shipped)
+    pred_plain_full = hold_prof.predict_passes(mode=q.PLAN_PROFILED, profile=train_prof)
     summary = {
         "circuits": int(done), "passes": int(len(y)), "train_passes": int((~held).sum()),
         "heldout_passes": int(held.sum()), "final_train_loss": loss, "train_seconds": train_s,
         "mape_learned": mape(pred_mlp, true), "mape_plain": mape(pred_plain, true),
+        "mape_plain_full_table": mape(pred_plain_full, true),
+        "plain_table_passes": int(len(train_prof.records())), "shipped_profile_passes": int(len(shipped.records())),
         "median_ape_learned": float(np.median(np.abs(pred_mlp - true) / true)),
         "median_ape_plain": float(np.median(np.abs(pred_plain - true) / true)),
     }

@@ -2,10 +2,13 @@
 // cost model and the cheapest is kept -- the profile-guided activation of an
 // optimisation (paper Sec. III-D), with the profile's measured pass times as
 // the plain cost table and a trained perceptron as the learned one.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "mlp.hpp"
@@ -14,71 +17,104 @@
 
 namespace qops {
 
-// Plain cost table: pass time / (2^n / 2^30) fitted as a linear function of
-// a few pass features (pass type, operation counts by class, matrix-core
-// flops, tile shape) by least squares over the profile's pass records.
-static const int kPlainIdx[] = {2, 3, 4, 5, 6, 8, 9, 10, 11, 12, 13, 15, 16, 17, 62};
-static constexpr int kPlainDim = sizeof(kPlainIdx) / sizeof(int);
+// Plain cost table (the profile-guided table of measured costs): a pass's
+// time per amplitude, looked up by the shape of the pass -- its kernel kind,
+// tile width, register/wave split, widest dense block and number of device
+// operations (exact up to 16, then powers of two) -- as the median over the
+// profile's passes of that shape.  Shapes the profile never saw fall back to
+// coarser keys (dropping the wave split, then bucketing the operation count
+// by powers of two, then the block width) and finally to the median of the
+// pass kind.  On a GPU every pass streams the whole state, so the high bits
+// a pass touches (the paper's stride) matter little; what it carries does.
+namespace {
 
-static bool solve_spd(std::vector<double>& A, std::vector<double>& b, int d)
+int feat_round(float v, float scale) { return (int)std::lround((double)v * scale); }
+
+struct PassShape {
+    int type, L, W, maxk, nops;
+};
+
+PassShape shape_of(const float* f)
 {
-    // Cholesky with a small ridge for rank-deficient designs
-    for (int i = 0; i < d; ++i) A[i * d + i] += 1e-9 + 1e-6 * A[i * d + i];
-    for (int j = 0; j < d; ++j) {
-        double s = A[j * d + j];
-        for (int k = 0; k < j; ++k) s -= A[j * d + k] * A[j * d + k];
-        if (s <= 0) return false;
-        A[j * d + j] = std::sqrt(s);
-        for (int i = j + 1; i < d; ++i) {
-            double t = A[i * d + j];
-            for (int k = 0; k < j; ++k) t -= A[i * d + k] * A[j * d + k];
-            A[i * d + j] = t / A[j * d + j];
-        }
-    }
-    for (int i = 0; i < d; ++i) {
-        double t = b[i];
-        for (int k = 0; k < i; ++k) t -= A[i * d + k] * b[k];
-        b[i] = t / A[i * d + i];
-    }
-    for (int i = d - 1; i >= 0; --i) {
-        double t = b[i];
-        for (int k = i + 1; k < d; ++k) t -= A[k * d + i] * b[k];
-        b[i] = t / A[i * d + i];
-    }
-    return true;
+    PassShape s;
+    s.type = 0;
+    for (int t = 0; t < 5; ++t)
+        if (f[2 + t] > 0.5f) s.type = t;
+    s.L = feat_round(f[7], 16.f);
+    s.W = feat_round(f[16], 1.f);
+    s.maxk = feat_round(f[14], 6.f);
+    s.nops = feat_round(f[54], 64.f);
+    return s;
 }
 
-static bool fit_plain(const qops_profile& pr, std::vector<double>& theta)
+int ops_bucket(int nops, bool fine)
+{
+    if (fine && nops <= 16) return nops;
+    int b = 17;
+    for (int v = 32; v <= nops; v <<= 1) ++b;
+    return fine ? b : (nops <= 1 ? 0 : 1 + (31 - __builtin_clz((unsigned)nops)));
+}
+
+// key levels, finest first
+uint64_t shape_key(const PassShape& s, int level)
+{
+    uint64_t k = (uint64_t)s.type;
+    if (level <= 3) k = k * 64 + (uint64_t)s.L;
+    if (level <= 0) k = k * 8 + (uint64_t)s.W;
+    if (level <= 2) k = k * 8 + (uint64_t)s.maxk;
+    if (level <= 1) k = k * 64 + (uint64_t)ops_bucket(s.nops, level == 0);
+    return k * 8 + (uint64_t)level;
+}
+constexpr int kLevels = 5;
+
+double amp_scale(const float* f)
+{
+    const double n = std::round((double)f[0] * 32.0);
+    return std::ldexp(1.0, (int)n - 30);
+}
+
+double median(std::vector<double>& v)
+{
+    const size_t m = v.size() / 2;
+    std::nth_element(v.begin(), v.begin() + (long)m, v.end());
+    double x = v[m];
+    if (v.size() % 2 == 0) {
+        const double lo = *std::max_element(v.begin(), v.begin() + (long)m);
+        x = 0.5 * (x + lo);
+    }
+    return x;
+}
+
+}  // namespace
+
+struct PlainTable {
+    std::unordered_map<uint64_t, double> cost;   // seconds at 30 qubits
+};
+
+static bool fit_plain(const qops_profile& pr, PlainTable& tab)
 {
     const size_t np = pr.recs.size();
     if (np == 0) return false;
-    const int d = kPlainDim;
-    std::vector<double> A((size_t)d * d, 0.0), b(d, 0.0);
+    std::unordered_map<uint64_t, std::vector<double>> bins;
     for (size_t i = 0; i < np; ++i) {
         const float* f = &pr.feats[i * kNumFeatures];
-        const double n = f[0] * 32.0;
-        const double scale = std::ldexp(1.0, (int)std::lround(n) - 30);
-        const double y = pr.recs[i].seconds / scale;
-        double x[kPlainDim];
-        for (int j = 0; j < d; ++j) x[j] = f[kPlainIdx[j]];
-        for (int r = 0; r < d; ++r) {
-            b[r] += x[r] * y;
-            for (int c = 0; c < d; ++c) A[(size_t)r * d + c] += x[r] * x[c];
-        }
+        const PassShape s = shape_of(f);
+        const double y = pr.recs[i].seconds / amp_scale(f);
+        for (int lv = 0; lv < kLevels; ++lv) bins[shape_key(s, lv)].push_back(y);
     }
-    if (!solve_spd(A, b, d)) return false;
-    theta = b;
+    tab.cost.clear();
+    for (auto& kv : bins) tab.cost[kv.first] = median(kv.second);
     return true;
 }
 
-double plain_predict(const std::vector<double>& theta, const float* f)
+static double plain_predict(const PlainTable& tab, const float* f)
 {
-    const double n = f[0] * 32.0;
-    const double scale = std::ldexp(1.0, (int)std::lround(n) - 30);
-    double y = 0;
-    for (int j = 0; j < kPlainDim; ++j) y += theta[j] * f[kPlainIdx[j]];
-    const double floor_s = 2e-6;   // a launch never costs less than this
-    return std::max(y * scale, floor_s);
+    const PassShape s = shape_of(f);
+    for (int lv = 0; lv < kLevels; ++lv) {
+        auto it = tab.cost.find(shape_key(s, lv));
+        if (it != tab.cost.end()) return it->second * amp_scale(f);
+    }
+    return 2e-6;   // no pass of this kind profiled: a launch's floor
 }
 
 // The network predicts ln(seconds) scaled to 30 qubits; f[0] is n / 32.
@@ -88,7 +124,7 @@ static double learned_seconds(float y, const float* f)
     return std::exp((double)y + (n - 30.0) * 0.69314718055994530942);
 }
 
-static double price(const Plan& p, const qops_plan_opts* o, const std::vector<double>& theta)
+static double price(const Plan& p, const qops_plan_opts* o, const PlainTable& theta)
 {
     std::vector<float> f(p.passes.size() * kNumFeatures);
     for (size_t i = 0; i < p.passes.size(); ++i) pass_features(p, p.passes[i], &f[i * kNumFeatures]);
@@ -114,7 +150,7 @@ int32_t build_priced_plan(int n, int prec, const int32_t* l2p, const qops_gate* 
         return QOPS_OK;
     }
     const bool learned = opts->mode == QOPS_PLAN_LEARNED && opts->model;
-    std::vector<double> theta;
+    PlainTable theta;
     if (!learned) {
         if (!opts->profile) return set_error(QOPS_INVALID_ARG, "PROFILED mode needs a profile (opts.profile)");
         if (!fit_plain(*opts->profile, theta)) return set_error(QOPS_INVALID_ARG, "profile has no usable pass records");
@@ -160,13 +196,56 @@ extern "C" {
 int32_t qops_plan_predict(const qops_plan* p, const qops_plan_opts* opts, double* seconds)
 {
     if (!p || !opts || !seconds) return qops::set_error(QOPS_INVALID_ARG, "null argument");
-    std::vector<double> theta;
+    qops::PlainTable theta;
     if (!(opts->mode == QOPS_PLAN_LEARNED && opts->model)) {
         if (!opts->profile || !qops::fit_plain(*opts->profile, theta))
             return qops::set_error(QOPS_INVALID_ARG, "need a model (LEARNED) or a profile");
     }
     *seconds = qops::price(p->p, opts, theta);
     return QOPS_OK;
+}
+
+int32_t qops_profile_compact(const qops_profile* src, qops_profile** out)
+{
+    try {
+        if (!src || !out) return qops::set_error(QOPS_INVALID_ARG, "null argument");
+        *out = nullptr;
+        // per finest shape: the passes at the 10th, 30th, 50th, 70th and 90th
+        // percentile of the per-amplitude time (all of them if fewer than 5)
+        std::unordered_map<uint64_t, std::vector<std::pair<double, size_t>>> bins;
+        for (size_t i = 0; i < src->recs.size(); ++i) {
+            const float* f = &src->feats[i * qops::kNumFeatures];
+            bins[qops::shape_key(qops::shape_of(f), 0)].push_back({src->recs[i].seconds / qops::amp_scale(f), i});
+        }
+        std::vector<uint64_t> keys;
+        for (auto& kv : bins) keys.push_back(kv.first);
+        std::sort(keys.begin(), keys.end());
+        std::unique_ptr<qops_profile> c(new qops_profile());
+        c->n = src->n;
+        c->prec = src->prec;
+        c->lcount = src->lcount;
+        c->pcount = src->pcount;
+        for (uint64_t k : keys) {
+            auto& v = bins[k];
+            std::sort(v.begin(), v.end());
+            std::vector<size_t> pick;
+            if (v.size() <= 5) {
+                for (auto& e : v) pick.push_back(e.second);
+            } else {
+                for (double qn : {0.1, 0.3, 0.5, 0.7, 0.9}) pick.push_back(v[(size_t)(qn * (double)(v.size() - 1) + 0.5)].second);
+            }
+            for (size_t i : pick) {
+                c->recs.push_back(src->recs[i]);
+                c->feats.insert(c->feats.end(), src->feats.begin() + (long)(i * qops::kNumFeatures),
+                                src->feats.begin() + (long)((i + 1) * qops::kNumFeatures));
+                c->total += src->recs[i].seconds;
+            }
+        }
+        *out = c.release();
+        return QOPS_OK;
+    } catch (...) {
+        return qops::set_error(QOPS_OUT_OF_MEMORY, "host allocation failed");
+    }
 }
 
 int32_t qops_profile_predict_passes(const qops_profile* pr, const qops_plan_opts* opts, double* out)
@@ -179,7 +258,7 @@ int32_t qops_profile_predict_passes(const qops_profile* pr, const qops_plan_opts
         for (size_t i = 0; i < np; ++i) out[i] = qops::learned_seconds(y[i], &pr->feats[i * qops::kNumFeatures]);
         return QOPS_OK;
     }
-    std::vector<double> theta;
+    qops::PlainTable theta;
     if (!opts->profile || !qops::fit_plain(*opts->profile, theta))
         return qops::set_error(QOPS_INVALID_ARG, "need a model (LEARNED) or a profile");
     for (size_t i = 0; i < np; ++i) out[i] = qops::plain_predict(theta, &pr->feats[i * qops::kNumFeatures]);

