@@ -511,11 +511,15 @@ def host_tier(n: int, g: int = 2, amax: int = 1):
         t.init_basis(x0)
         st = t.run(c.gates, remap=remap)
         l2p = t.layout()
-        view = t.host_view()
         phys = np.zeros(ys.size, dtype=np.uint64)
         for qb in range(n):
             phys |= ((ys >> np.uint64(qb)) & np.uint64(1)) << np.uint64(int(l2p[qb]))
-        got = view[phys.astype(np.int64)].astype(np.complex128)
+        seg = (phys >> np.uint64(n - g)).astype(np.int64)
+        off = (phys & np.uint64(2 ** (n - g) - 1)).astype(np.int64)
+        got = np.zeros(ys.size, dtype=np.complex128)
+        for sgi in range(2 ** g):
+            m = seg == sgi
+            got[m] = t.segment_view(sgi)[off[m]]
         err = float(np.max(np.abs(got - ref)))
         tag = "placed" if remap else "identity"
         res[tag] = {"seconds": round(st["seconds"], 3), "stages": st["stages"], "groups": st["groups"],

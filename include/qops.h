@@ -492,15 +492,17 @@ typedef struct qops_tier_stats {
 int32_t qops_tier_opts_default(qops_tier_opts* opts);
 /* n qubits (2..34), g = global_bits segment bits (1..min(8, n-1)),
  * max_active in 1..g.  host_state: caller's PINNED buffer of >= 2^n
- * amplitudes (kept alive until destroy), or null for a library-owned
- * hipHostMalloc buffer.  stream: the caller's stream for the group plans.
+ * amplitudes (kept alive until destroy), or null for library-owned pinned
+ * memory, one hipHostMalloc block per segment.  stream: the caller's stream for the group plans.
  * Errors: QOPS_UNSUPPORTED / QOPS_INVALID_ARG for shapes, QOPS_OUT_OF_MEMORY
  * or QOPS_HIP_ERROR for allocations.  The state is not initialised. */
 int32_t qops_tier_create(int32_t n, int32_t precision, int32_t global_bits, int32_t max_active, void* host_state,
                          size_t bytes, void* stream, qops_tier** out);
 int32_t qops_tier_destroy(qops_tier* t);
-/* Host pointer of the state (physical order) and its size in bytes. */
-int32_t qops_tier_state_pointer(qops_tier* t, void** host, size_t* bytes);
+/* Host pointer and size in bytes of segment s (0 <= s < 2^g): physical
+ * amplitudes s * 2^(n-g) .. (s+1) * 2^(n-g) - 1.  A library-owned state has
+ * one pinned allocation per segment (the paper's one file per segment). */
+int32_t qops_tier_segment_pointer(qops_tier* t, int32_t segment, void** host, size_t* bytes);
 /* |x> in logical order, identity layout.  Blocking (host writes). */
 int32_t qops_tier_init_basis(qops_tier* t, uint64_t x);
 /* Runs a gate list (opts null = defaults); stats may be null.  Blocking.

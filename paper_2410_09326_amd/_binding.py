@@ -164,7 +164,7 @@ SIGNATURES = {
     "qops_tier_opts_default": (_I32, [ctypes.POINTER(TierOpts)]),
     "qops_tier_create": (_I32, [_I32, _I32, _I32, _I32, _VP, _SZ, _VP, ctypes.POINTER(_VP)]),
     "qops_tier_destroy": (_I32, [_VP]),
-    "qops_tier_state_pointer": (_I32, [_VP, ctypes.POINTER(_VP), ctypes.POINTER(_SZ)]),
+    "qops_tier_segment_pointer": (_I32, [_VP, _I32, ctypes.POINTER(_VP), ctypes.POINTER(_SZ)]),
     "qops_tier_init_basis": (_I32, [_VP, _U64]),
     "qops_tier_run": (_I32, [_VP, ctypes.POINTER(Gate), _SZ, ctypes.POINTER(TierOpts), ctypes.POINTER(TierStats)]),
     "qops_tier_plan": (_I32, [_I32, _I32, _I32, _IP, ctypes.POINTER(Gate), _SZ, _I32, ctypes.POINTER(TierStats), _IP]),
@@ -750,6 +750,7 @@ class TieredSimulator:
         import torch
         self.n = n
         self.precision = precision
+        self.global_bits = global_bits
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -798,12 +799,12 @@ class TieredSimulator:
         check(lib().qops_tier_read_state(self.handle, out.ctypes.data_as(ctypes.c_void_p), order))
         return out
 
-    def host_view(self) -> np.ndarray:
-        """The pinned host state itself (physical order, no copy); valid
-        until close()."""
+    def segment_view(self, s: int) -> np.ndarray:
+        """Segment s of the pinned host state (physical amplitudes
+        s * 2^(n-g) onwards, no copy); valid until close()."""
         p = ctypes.c_void_p()
         nb = ctypes.c_size_t()
-        check(lib().qops_tier_state_pointer(self.handle, ctypes.byref(p), ctypes.byref(nb)))
+        check(lib().qops_tier_segment_pointer(self.handle, int(s), ctypes.byref(p), ctypes.byref(nb)))
         dt = np.complex64 if self.precision == C64 else np.complex128
         buf = (ctypes.c_char * nb.value).from_address(p.value)
         return np.frombuffer(buf, dtype=dt)

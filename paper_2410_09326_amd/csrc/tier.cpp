@@ -307,8 +307,8 @@ static Err plan_tier(int n, int prec, int g, int amax, std::vector<int>& l2p, co
 struct qops_tier {
     int n = 0, prec = 0, g = 0, amax = 1;
     int nloc = 0;
-    void* host = nullptr;
-    bool host_owned = false;
+    std::vector<char*> seg;                // host segment s (2^(n-g) amplitudes each)
+    bool host_owned = false;               // segments allocated by the library, one pinned block each
     size_t bytes = 0;
     void* dev[2] = {nullptr, nullptr};
     size_t slot_bytes = 0;
@@ -351,10 +351,16 @@ uint64_t basis_phys(const qops_tier* t)
     return phys;
 }
 
+size_t seg_bytes_of(const qops_tier* t) { return ((size_t)1 << t->nloc) * amp_size(t->prec); }
+
+char* amp_ptr(qops_tier* t, uint64_t phys)
+{
+    return t->seg[phys >> t->nloc] + (phys & ((1ull << t->nloc) - 1ull)) * amp_size(t->prec);
+}
+
 void put_one(qops_tier* t, uint64_t phys, bool one)
 {
-    const size_t asz = amp_size(t->prec);
-    char* p = static_cast<char*>(t->host) + phys * asz;
+    char* p = amp_ptr(t, phys);
     if (t->prec == QOPS_C64) {
         const float v[2] = {one ? 1.f : 0.f, 0.f};
         std::memcpy(p, v, sizeof(v));
@@ -366,10 +372,9 @@ void put_one(qops_tier* t, uint64_t phys, bool one)
 
 int32_t tier_copy_basis(qops_tier* t)
 {
-    const size_t asz = amp_size(t->prec);
     const uint64_t phys = basis_phys(t);
-    parallel_zero(t->host, t->bytes);
-    char* p = static_cast<char*>(t->host) + phys * asz;
+    for (char* sp : t->seg) parallel_zero(sp, seg_bytes_of(t));
+    char* p = amp_ptr(t, phys);
     if (t->prec == QOPS_C64) {
         const float one[2] = {1.f, 0.f};
         std::memcpy(p, one, sizeof(one));
@@ -392,7 +397,7 @@ int32_t tier_group(qops_tier* t, TierGroup& grp, int m, size_t item, bool after_
     if (e == hipSuccess && after_prev_stage && item >= 1) e = hipStreamWaitEvent(t->copy_in, t->stored[slot ^ 1], 0);
     for (size_t j = 0; j < grp.segments.size() && e == hipSuccess; ++j)
         e = hipMemcpyAsync(static_cast<char*>(t->dev[slot]) + j * seg_bytes,
-                           static_cast<char*>(t->host) + grp.segments[j] * seg_bytes, seg_bytes,
+                           t->seg[grp.segments[j]], seg_bytes,
                            hipMemcpyHostToDevice, t->copy_in);
     if (e == hipSuccess) e = hipEventRecord(t->loaded[slot], t->copy_in);
     if (e == hipSuccess) e = hipStreamWaitEvent(t->stream, t->loaded[slot], 0);
@@ -407,7 +412,7 @@ int32_t tier_group(qops_tier* t, TierGroup& grp, int m, size_t item, bool after_
     e = hipEventRecord(t->computed[slot], t->stream);
     if (e == hipSuccess) e = hipStreamWaitEvent(t->copy_out, t->computed[slot], 0);
     for (size_t j = 0; j < grp.segments.size() && e == hipSuccess; ++j)
-        e = hipMemcpyAsync(static_cast<char*>(t->host) + grp.segments[j] * seg_bytes,
+        e = hipMemcpyAsync(t->seg[grp.segments[j]],
                            static_cast<char*>(t->dev[slot]) + j * seg_bytes, seg_bytes, hipMemcpyDeviceToHost,
                            t->copy_out);
     if (e == hipSuccess) e = hipEventRecord(t->stored[slot], t->copy_out);
@@ -469,20 +474,31 @@ int32_t qops_tier_create(int32_t n, int32_t precision, int32_t global_bits, int3
         t->l2p.resize(n);
         for (int q = 0; q < n; ++q) t->l2p[q] = q;
         hipError_t e;
-        if (host_state) {
-            if (bytes < t->bytes) return set_error(QOPS_INVALID_ARG, "host buffer is smaller than 2^n amplitudes");
-            t->host = host_state;
-        } else {
-            e = hipHostMalloc(&t->host, t->bytes, hipHostMallocDefault);
-            if (e != hipSuccess) return hip_fail(e, "pinned host state");
-            t->host_owned = true;
-        }
-        t->slot_bytes = ((size_t)1 << (t->nloc + max_active)) * amp_size(precision);
+        const size_t segb = ((size_t)1 << t->nloc) * amp_size(precision);
+        t->seg.assign((size_t)1 << global_bits, nullptr);
         auto cleanup = [&]() {
             for (void* d : t->dev)
                 if (d) (void)hipFree(d);
-            if (t->host_owned) (void)hipHostFree(t->host);
+            if (t->host_owned)
+                for (char* sp : t->seg)
+                    if (sp) (void)hipHostFree(sp);
         };
+        if (host_state) {
+            if (bytes < t->bytes) return set_error(QOPS_INVALID_ARG, "host buffer is smaller than 2^n amplitudes");
+            for (size_t sgi = 0; sgi < t->seg.size(); ++sgi) t->seg[sgi] = static_cast<char*>(host_state) + sgi * segb;
+        } else {
+            t->host_owned = true;
+            for (size_t sgi = 0; sgi < t->seg.size(); ++sgi) {
+                void* sp = nullptr;
+                e = hipHostMalloc(&sp, segb, hipHostMallocDefault);
+                if (e != hipSuccess) {
+                    cleanup();
+                    return hip_fail(e, "pinned host segment");
+                }
+                t->seg[sgi] = static_cast<char*>(sp);
+            }
+        }
+        t->slot_bytes = ((size_t)1 << (t->nloc + max_active)) * amp_size(precision);
         for (int s = 0; s < 2; ++s) {
             e = hipMalloc(&t->dev[s], t->slot_bytes);
             if (e != hipSuccess) {
@@ -523,16 +539,19 @@ int32_t qops_tier_destroy(qops_tier* t)
     if (t->copy_in) (void)hipStreamDestroy(t->copy_in);
     if (t->copy_out) (void)hipStreamDestroy(t->copy_out);
     if (t->scratch) (void)hipFree(t->scratch);
-    if (t->host_owned && t->host) (void)hipHostFree(t->host);
+    if (t->host_owned)
+        for (char* sp : t->seg)
+            if (sp) (void)hipHostFree(sp);
     delete t;
     return QOPS_OK;
 }
 
-int32_t qops_tier_state_pointer(qops_tier* t, void** host, size_t* bytes)
+int32_t qops_tier_segment_pointer(qops_tier* t, int32_t segment, void** host, size_t* bytes)
 {
     if (!t || !host) return set_error(QOPS_INVALID_ARG, "null argument");
-    *host = t->host;
-    if (bytes) *bytes = t->bytes;
+    if (segment < 0 || (size_t)segment >= t->seg.size()) return set_error(QOPS_INVALID_ARG, "segment out of range");
+    *host = t->seg[(size_t)segment];
+    if (bytes) *bytes = seg_bytes_of(t);
     return QOPS_OK;
 }
 
@@ -660,7 +679,7 @@ int32_t qops_tier_expect_z(qops_tier* t, double* out)
             const int slot = (int)(s & 1);
             if (s >= 2) e = hipStreamWaitEvent(t->copy_in, t->stored[slot], 0);
             if (e == hipSuccess)
-                e = hipMemcpyAsync(t->dev[slot], static_cast<char*>(t->host) + s * seg_bytes, seg_bytes,
+                e = hipMemcpyAsync(t->dev[slot], t->seg[s], seg_bytes,
                                    hipMemcpyHostToDevice, t->copy_in);
             if (e == hipSuccess) e = hipEventRecord(t->loaded[slot], t->copy_in);
             if (e == hipSuccess) e = hipStreamWaitEvent(t->stream, t->loaded[slot], 0);
@@ -697,19 +716,19 @@ int32_t qops_tier_read_state(qops_tier* t, void* host, int32_t order)
     hipError_t e = hipStreamSynchronize(t->copy_out);
     if (e != hipSuccess) return hip_fail(e, "tier read_state");
     const size_t asz = amp_size(t->prec);
+    const size_t segb = seg_bytes_of(t);
     if (order == QOPS_ORDER_PHYSICAL) {
-        std::memcpy(host, t->host, t->bytes);
+        for (size_t sgi = 0; sgi < t->seg.size(); ++sgi) std::memcpy(static_cast<char*>(host) + sgi * segb, t->seg[sgi], segb);
         return QOPS_OK;
     }
     if (order != QOPS_ORDER_LOGICAL) return set_error(QOPS_INVALID_ARG, "bad order");
     const uint64_t N = 1ull << t->n;
-    const char* src = static_cast<const char*>(t->host);
     char* dst = static_cast<char*>(host);
     for (uint64_t x = 0; x < N; ++x) {
         uint64_t p = 0;
         for (int q = 0; q < t->n; ++q)
             if ((x >> q) & 1ull) p |= 1ull << t->l2p[q];
-        std::memcpy(dst + x * asz, src + p * asz, asz);
+        std::memcpy(dst + x * asz, amp_ptr(t, p), asz);
     }
     return QOPS_OK;
 }
