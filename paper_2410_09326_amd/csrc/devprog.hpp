@@ -23,6 +23,10 @@ enum OpType : int32_t {
 // OP_1Q_REG / OP_1Q_LANE: b = 1 marks an exact X (pure exchange, no arithmetic).
 // OP_MFMA / OP_DIAG_LDS / OP_DENSE_LDS in an LDS tile pass: b = 1 means `coef` is an offset
 // into the coefficients staged in LDS, b = 0 an offset into global memory.
+// OP_MFMA: c_reg (unused by LDS ops otherwise) holds QOPS_MFMA_WIDE when the
+// block runs in the 32x32x2 three-product form (5-qubit blocks on the
+// largest complex64 tile); its coefficients then follow that layout.
+#define QOPS_MFMA_WIDE 1u
 
 // Encoded source of one bit of a diagonal's table index (OP_DIAG pos[i]).
 enum BitSrc : int32_t { SRC_LANE = 0, SRC_WAVE = 1, SRC_REG = 2, SRC_GLOB = 3 };

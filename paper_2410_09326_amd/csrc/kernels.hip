@@ -688,6 +688,166 @@ __device__ __forceinline__ void mfma_core(typename CxT<T>::V* lds, int L, const 
     }
 }
 
+// 32x32x2 three-product form of a complex 2^K x 2^K block on a complex64 LDS
+// tile (instantiated for K = 5: a 6-qubit block's fragments would take 96
+// registers, which do not fit beside the next tile's prefetch at two
+// work-groups per CU).  The block's rows form 2^(K-5) row blocks of 32, one
+// per wave of a column group (K = 5: four groups of one wave); a column
+// block is 32 columns (groups of 2^K amplitudes), which differ in the five
+// tile positions of op.c_lane.  In k-step ks lane l feeds input 2 ks + l/32
+// of column l%32 -- one (re, im) read serves the three products T1 = A x,
+// T2 = B y, T3 = (A + B)(x + y) -- and the result row 8 (r/4) + 4 (l/32) +
+// r%4 of column l%32 comes back in register r.  A fragments: (rb, ks, m)
+// lane l holds the m-th part (A, B, A + B) of U[32 rb + l%32][2 ks + l/32],
+// either in registers (`ar`, the pass's hoisted block) or read from the
+// LDS-staged coefficients one k-step ahead (`al`).  Per k-step the wave
+// issues three 64-cycle MFMAs against one LDS read and one add: half the
+// other instructions per MFMA cycle of the 16x16x4 form.
+template <int K>
+struct WideShape {
+    static constexpr int KS = 1 << (K - 1);    // k-steps of 2 inputs
+    static constexpr int RB = 1 << (K - 5);    // row blocks of 32
+    static constexpr int RW = RB;              // waves per column group
+    static constexpr int CW = 4 / RW;          // column groups
+};
+template <int K>
+using WideFrag = float[3][WideShape<K>::KS];
+
+using F16 = float __attribute__((ext_vector_type(16)));
+
+template <int K>
+__device__ __forceinline__ void wide_load_a(WideFrag<K>& av, const float* __restrict__ A, int lane, int wave)
+{
+    using S = WideShape<K>;
+    const int rb = wave % S::RW;
+#pragma unroll
+    for (int ks = 0; ks < S::KS; ++ks)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) av[m][ks] = A[((rb * S::KS + ks) * 3 + m) * 64 + lane];
+}
+
+template <int K, int CH, bool AREG>
+__device__ __forceinline__ void mfma_core_wide(float2* lds, int L, const DevOp& op, const WideFrag<K>* ar,
+                                               const float* __restrict__ al, int lane, int wave)
+{
+    using S = WideShape<K>;
+    constexpr int KS = S::KS, RW = S::RW, CW = S::CW;
+    using V = float2;
+    const int rb = wave % RW, cg = wave / RW;
+    const int ncb = 1 << (L - K - 5);          // the planner keeps ncb a multiple of CW
+    const int nper = ncb / CW;
+    uint32_t bit[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) bit[j] = 1u << op.pos[j];
+    auto toff = [&](uint32_t s) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (s & (1u << j)) o |= bit[j];
+        return o;
+    };
+    const uint32_t gl = deposit_bits((uint32_t)(lane & 31), op.c_lane);
+    const uint32_t khalf = (uint32_t)(lane >> 5);
+    const uint32_t in_sw = swz(khalf ? bit[0] : 0u);
+    const uint32_t out_sw = swz(toff(4u * khalf)) ^ swz(toff(32u * (uint32_t)rb));
+    const uint32_t wmask = op.c_wave;
+    const uint32_t wstep = deposit_bits((uint32_t)CW, wmask);
+    uint32_t gblk = deposit_bits((uint32_t)cg, wmask);
+    const float* __restrict__ alw = al + (size_t)rb * KS * 3 * 64 + lane;
+    __builtin_amdgcn_s_setprio(1);
+    for (int i0 = 0; i0 < nper; i0 += CH) {
+        F16 d1[CH], d2[CH], d3[CH];
+        uint32_t gsw[CH], gcol[CH], gin[CH];
+        bool ok[CH];
+        sfor<CH>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            ok[c] = i0 + c < nper;
+            gcol[c] = gl | gblk;
+            gsw[c] = swz(gcol[c]);
+            gin[c] = (gsw[c] ^ in_sw) * (uint32_t)sizeof(V);
+            gblk = ((gblk | ~wmask) + wstep) & wmask;
+        });
+        // inputs, their sums and (LDS-staged blocks) the A fragments one
+        // k-step ahead of the MFMAs that use them
+        V bq[2][CH];
+        float bs[2][CH];
+        float aq[2][3];
+        auto load_a = [&](auto kc, float* a) {
+            constexpr int ks = decltype(kc)::value;
+            if constexpr (AREG) {
+                a[0] = (*ar)[0][ks];
+                a[1] = (*ar)[1][ks];
+                a[2] = (*ar)[2][ks];
+            } else {
+                a[0] = alw[(ks * 3 + 0) * 64];
+                a[1] = alw[(ks * 3 + 1) * 64];
+                a[2] = alw[(ks * 3 + 2) * 64];
+            }
+        };
+        sfor<CH>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            bq[0][c] = lds_at(lds, gin[c]);
+        });
+        load_a(std::integral_constant<int, 0>{}, aq[0]);
+        sfor<CH>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            bs[0][c] = bq[0][c].x + bq[0][c].y;
+        });
+        sfor<KS>([&](auto kc) {
+            constexpr int ks = decltype(kc)::value;
+            constexpr int cur = ks & 1;
+            if constexpr (ks + 1 < KS) {
+                const uint32_t nx = swz(toff((uint32_t)(2 * (ks + 1)))) * (uint32_t)sizeof(V);
+                sfor<CH>([&](auto cc) {
+                    constexpr int c = decltype(cc)::value;
+                    bq[cur ^ 1][c] = lds_at(lds, gin[c] ^ nx);
+                });
+                if constexpr (!AREG) load_a(std::integral_constant<int, ks + 1>{}, aq[cur ^ 1]);
+            }
+            if constexpr (AREG) load_a(kc, aq[cur]);
+            __builtin_amdgcn_sched_barrier(0);
+            sfor<CH>([&](auto cc) {
+                constexpr int c = decltype(cc)::value;
+                if constexpr (ks == 0) {
+                    const F16 z = {};
+                    d1[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(aq[cur][0], bq[cur][c].x, z, 0, 0, 0);
+                    d2[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(aq[cur][1], bq[cur][c].y, z, 0, 0, 0);
+                    d3[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(aq[cur][2], bs[cur][c], z, 0, 0, 0);
+                } else {
+                    d1[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(aq[cur][0], bq[cur][c].x, d1[c], 0, 0, 0);
+                    d2[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(aq[cur][1], bq[cur][c].y, d2[c], 0, 0, 0);
+                    d3[c] = __builtin_amdgcn_mfma_f32_32x32x2f32(aq[cur][2], bs[cur][c], d3[c], 0, 0, 0);
+                }
+            });
+            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (ks + 1 < KS) {
+                sfor<CH>([&](auto cc) {
+                    constexpr int c = decltype(cc)::value;
+                    bs[cur ^ 1][c] = bq[cur ^ 1][c].x + bq[cur ^ 1][c].y;
+                });
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        });
+        if constexpr (RW > 1) __syncthreads();   // every wave of the group has read these columns
+        sfor<CH>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            if (ok[c] && (gcol[c] & op.c_tile) == op.c_tile) {
+                uint32_t g_out = (gsw[c] ^ out_sw) * (uint32_t)sizeof(V);
+                asm volatile("" : "+v"(g_out));
+                sfor<16>([&](auto rc) {
+                    constexpr int r = decltype(rc)::value;
+                    constexpr uint32_t row = 8u * (r / 4) + (r % 4);
+                    V w;
+                    w.x = d1[c][r] - d2[c][r];
+                    w.y = d3[c][r] - d1[c][r] - d2[c][r];
+                    lds_put(lds, g_out ^ (swz(toff(row)) * (uint32_t)sizeof(V)), w);
+                });
+            }
+        });
+    }
+    __builtin_amdgcn_s_setprio(0);
+}
+
 template <int K, typename T>
 __device__ void mfma_lds(typename CxT<T>::V* lds, int L, const DevOp& op, const T* __restrict__ A, int lane,
                          int wave)
@@ -699,11 +859,31 @@ __device__ void mfma_lds(typename CxT<T>::V* lds, int L, const DevOp& op, const 
 
 // Matrix-core blocks of at most KMAX qubits (a kernel that keeps a larger
 // block's fragments resident dispatches only the small ones here).
-template <typename T, int KMAX = 6>
+// Blocks flagged QOPS_MFMA_WIDE (complex64, 5 qubits) run the 32x32x2 form
+// with their fragments read per k-step, WCH column blocks in flight.  WMODE
+// says which forms a kernel can meet, so that it compiles only those: 0 =
+// never the wide one, 1 = either, 2 = the wide one for every 5-qubit block
+// (complex64 on the largest tile).
+template <typename T, int KMAX = 6, int WCH = 2, int WMODE = 0>
 __device__ void mfma_dispatch(typename CxT<T>::V* lds, int L, const DevOp& op, const T* __restrict__ A, int lane,
                               int wave)
 {
     if (op.a > KMAX) return;
+    if constexpr (sizeof(T) == 4 && WMODE > 0) {
+        if (op.a == 5 && (WMODE == 2 || (op.c_reg & QOPS_MFMA_WIDE))) {
+            mfma_core_wide<5, WCH, false>(lds, L, op, nullptr, A, lane, wave);
+            return;
+        }
+    }
+    if constexpr (WMODE == 2) {
+        switch (op.a) {
+        case 3: mfma_lds<3, T>(lds, L, op, A, lane, wave); break;
+        case 4: mfma_lds<4, T>(lds, L, op, A, lane, wave); break;
+        case 6: if constexpr (KMAX >= 6) mfma_lds<6, T>(lds, L, op, A, lane, wave); break;
+        default: break;
+        }
+        return;
+    }
     switch (op.a) {
     case 3: mfma_lds<3, T>(lds, L, op, A, lane, wave); break;
     case 4: mfma_lds<4, T>(lds, L, op, A, lane, wave); break;
@@ -1099,12 +1279,19 @@ tile_lds_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict__
         for (int i = tid; i < hp->coef_n; i += 256) lcoef[i] = src[i];
     }
     constexpr int HKK = HK > 0 ? HK : 3;
+    // the full complex64 tile keeps its hoisted block in the 32x32x2 layout
+    // complex64 on the full tile runs its 5-qubit blocks in the 32x32x2 form
+    // (a hoisted 5-qubit block keeps that form's fragments)
+    constexpr bool WFULL = sizeof(T) == 4 && FULL;
+    constexpr bool HWIDE = WFULL && HK == 5;
     MfmaFrag<HKK, T> hav;
+    WideFrag<5> haw;
     const int hoist = HK > 0 ? hp->hoist : -1;
     if constexpr (HK > 0) {
         __syncthreads();   // staged coefficients visible
         const DevOp hop = prog[hoist];   // never staged: read from global memory once
-        mfma_load_a<HKK, T>(hav, coef + hop.coef, lane, wave);
+        if constexpr (HWIDE) wide_load_a<5>(haw, reinterpret_cast<const float*>(coef) + hop.coef, lane, wave);
+        else mfma_load_a<HKK, T>(hav, coef + hop.coef, lane, wave);
     }
     // element e = 256 u + tid: bits 0..F-1 of tid are physical bits 0..F-1
     // (F = QOPS_LDS_FIXED_BITS, contiguous in memory), bits F..7 of tid
@@ -1166,9 +1353,19 @@ tile_lds_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict__
             if (op.type == OP_DENSE_LDS) {
                 dense_lds_dispatch<T>(lds, L, op, cf, tid, 256);
             } else if (op.type == OP_MFMA) {
-                if constexpr (HK > 0) {
+                if constexpr (HWIDE) {
+                    if (i == hoist) mfma_core_wide<5, 1, true>(lds, L, op, &haw, nullptr, lane, wave);
+                    else mfma_dispatch<T, 5, 1, 2>(lds, L, op, cf, lane, wave);
+                } else if constexpr (WFULL && HK > 0) {
+                    // beside a hoisted 6-qubit block, one column block of the
+                    // 5-qubit ones in flight
+                    if (i == hoist) mfma_core<HKK, T>(lds, L, op, hav, lane, wave);
+                    else mfma_dispatch<T, 5, 1, 2>(lds, L, op, cf, lane, wave);
+                } else if constexpr (HK > 0) {
                     if (i == hoist) mfma_core<HKK, T>(lds, L, op, hav, lane, wave);
                     else mfma_dispatch<T, 5>(lds, L, op, cf, lane, wave);
+                } else if constexpr (WFULL) {
+                    mfma_dispatch<T, 6, 2, 2>(lds, L, op, cf, lane, wave);
                 } else {
                     mfma_dispatch<T>(lds, L, op, cf, lane, wave);
                 }
@@ -1940,11 +2137,12 @@ batch_pass_kernel(const BatchItem* __restrict__ items, int nitems, const BatchCi
         for (int j = 0; j < hp->nops; ++j) {
             const DevOp op = prog[j];
             if ((base & op.c_glob) != op.c_glob) continue;
-            const T* cf;
-            if constexpr (sizeof(T) == 4) cf = lcoef + op.coef;
-            else cf = op.b ? lcoef + op.coef : coef + op.coef;
+            // ops whose coefficients did not fit next to the tile (op.b = 0;
+            // in complex64 the block a single-circuit pass would keep in
+            // registers) read them from global memory
+            const T* cf = op.b ? lcoef + op.coef : coef + op.coef;
             if (op.type == OP_DENSE_LDS) dense_lds_dispatch<T>(lds, L, op, cf, tid, 256);
-            else if (op.type == OP_MFMA) mfma_dispatch<T>(lds, L, op, cf, lane, wave);
+            else if (op.type == OP_MFMA) mfma_dispatch<T, 6, 2, 1>(lds, L, op, cf, lane, wave);
             else if (op.type == OP_DIAG_LDS) diag_lds<T>(lds, L, op, cf, base, tid, 256);
             __syncthreads();
         }

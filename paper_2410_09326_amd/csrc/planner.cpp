@@ -548,6 +548,24 @@ static int push_mfma_coef(Plan& p, const std::vector<cd>& u, int k)
     return off;
 }
 
+// Coefficients of a 5- or 6-qubit block in the 32x32x2 three-product form
+// (complex64, largest LDS tile): fragment (rb, ks, m), lane l holds row
+// 32 rb + l % 32, column 2 ks + l / 32 of A (m = 0), B (1) or A + B (2);
+// 3 * 4^k values, as in the 16x16x4 form.
+static int push_mfma_coef_wide(Plan& p, const std::vector<cd>& u, int k)
+{
+    const int d = 1 << k, KS = d / 2, RB = d / 32;
+    const int off = (int)p.coef.size();
+    for (int rb = 0; rb < RB; ++rb)
+        for (int ks = 0; ks < KS; ++ks)
+            for (int m = 0; m < 3; ++m)
+                for (int l = 0; l < 64; ++l) {
+                    const cd v = u[(size_t)(32 * rb + (l & 31)) * d + (2 * ks + (l >> 5))];
+                    p.coef.push_back(m == 0 ? v.real() : (m == 1 ? v.imag() : v.real() + v.imag()));
+                }
+    return off;
+}
+
 static void fill_runs(int n, int fixed, const std::vector<int>& up, PassHdr& h)
 {
     std::vector<bool> intile(n, false);
@@ -675,6 +693,29 @@ static void set_mfma_columns(DevOp& d, int k, int L)
     d.c_wave = all & ~opm & ~used;
 }
 
+// Columns of a block in the 32x32x2 form: half a wave reads (and writes) one
+// matrix index of 32 columns, which differ in the five positions of c_lane;
+// they hit 32 distinct banks when those positions cover the five bank
+// classes.  Positions are taken class by class, then filled up to five.
+static void set_mfma_columns_wide(DevOp& d, int k, int L)
+{
+    uint32_t opm = 0;
+    for (int j = 0; j < k; ++j) opm |= 1u << d.pos[j];
+    uint32_t used = 0, taken = 0;
+    for (int tp = 0; tp < L; ++tp) {
+        const uint32_t c = class_bit(tp);
+        if ((opm & (1u << tp)) || !c || (taken & c)) continue;
+        taken |= c;
+        used |= 1u << tp;
+    }
+    for (int tp = 0; tp < L && __builtin_popcount(used) < 5; ++tp)
+        if (!(opm & (1u << tp)) && !(used & (1u << tp))) used |= 1u << tp;
+    const uint32_t all = (L >= 32 ? ~0u : ((1u << L) - 1u));
+    d.c_lane = used;
+    d.c_wave = all & ~opm & ~used;
+    d.c_reg = QOPS_MFMA_WIDE;
+}
+
 // Which targets become matrix bit 0 (reads) and the write bit: the pair that
 // reaches the most distinct classes (ties keep the lower indices).
 static void best_bank_bits(const int* tp, int k, int L, int& j0, int& jw)
@@ -725,7 +766,7 @@ static void place_bank_bits(std::vector<cd>& m, int* t, int* tp, int k, int j0, 
 }
 
 template <typename F>
-static void emit_lds_op(Plan& p, const LOp& o, int L, F tpos, PassPlan& pp)
+static void emit_lds_op(Plan& p, const LOp& o, int L, F tpos, PassPlan& pp, bool wide_ok = false)
 {
     DevOp d;
     std::memset(&d, 0, sizeof(d));
@@ -751,7 +792,8 @@ static void emit_lds_op(Plan& p, const LOp& o, int L, F tpos, PassPlan& pp)
             m[2 * 4 + 1] = 1;
             m[15] = 1;
         }
-        if (o.kind == LOp::DENSE && use_mfma_for(p, k, L)) {
+        const bool wide = wide_ok && o.kind == LOp::DENSE && k == 5 && use_mfma_for(p, k, L);
+        if (o.kind == LOp::DENSE && use_mfma_for(p, k, L) && !wide) {
             int tp[6];
             for (int j = 0; j < k; ++j) tp[j] = tpos(t[j]);
             int j0 = 0, jw = 1;
@@ -768,9 +810,14 @@ static void emit_lds_op(Plan& p, const LOp& o, int L, F tpos, PassPlan& pp)
         d.a = k;
         if (use_mfma_for(p, k, L)) {
             d.type = OP_MFMA;
-            d.coef = push_mfma_coef(p, m, k);
             pp.n_mfma++;
-            set_mfma_columns(d, k, L);
+            if (wide) {
+                d.coef = push_mfma_coef_wide(p, m, k);
+                set_mfma_columns_wide(d, k, L);
+            } else {
+                d.coef = push_mfma_coef(p, m, k);
+                set_mfma_columns(d, k, L);
+            }
         } else {
             d.type = OP_DENSE_LDS;
             d.coef = push_coef(p, m);
@@ -970,7 +1017,10 @@ static void emit_tile_lds(Plan& p, PassPlan& pp)
             if (pp.up[u] == phys) return QOPS_LDS_FIXED_BITS + u;
         return -1;
     };
-    for (int li : pp.lop) emit_lds_op(p, p.lops[li], pp.L, tpos, pp);
+    // complex64 passes on the largest tile run their 5-qubit blocks in the
+    // 32x32x2 form
+    const bool wide_ok = p.prec == 0 && pp.L == 13;
+    for (int li : pp.lop) emit_lds_op(p, p.lops[li], pp.L, tpos, pp, wide_ok);
     h.nops = (int)p.dops.size() - h.op0;
     // stage the per-lane coefficients (matrix-core fragments, diagonal
     // tables) contiguously, as far as they fit next to the tile in LDS
@@ -1322,6 +1372,14 @@ static Err finish_plan(Plan& p, std::vector<LOp>& lowered, std::chrono::steady_c
                 for (int i = h.op0; i < h.op0 + h.nops; ++i)
                     if (i - h.op0 != h.hoist && p.dops[i].type == OP_MFMA && p.dops[i].a > 5)
                         return mkerr(QOPS_UNSUPPORTED, "internal: two 6-qubit matrix-core blocks in one LDS pass");
+            }
+            // the full-tile kernel runs every 5-qubit block in the 32x32x2
+            // form, the smaller tiles none
+            for (int i = h.op0; i < h.op0 + h.nops; ++i) {
+                const DevOp& d = p.dops[i];
+                const bool wide = d.type == OP_MFMA && (d.c_reg & QOPS_MFMA_WIDE) != 0;
+                if (d.type == OP_MFMA && wide != (pp.L == 13 && d.a == 5))
+                    return mkerr(QOPS_UNSUPPORTED, "internal: matrix-core block layout does not match the tile size");
             }
         }
     for (const PassPlan& pp : p.passes) {

@@ -65,6 +65,24 @@ def test_batch_fused_blocks(q, kf):
 
 
 @pytest.mark.gpu
+def test_batch_wide_blocks_on_the_full_tile(q):
+    """complex64 circuits of Haar blocks of 2..6 qubits on 2^13-amplitude
+    tiles: the 5- and 6-qubit blocks run the 32x32x2 matrix-core form, and
+    the block a single-circuit pass would keep in registers reads its
+    fragments from global memory."""
+    circs = [W.Circuit(c.n, c.gates, name=c.name) for c in
+             (W.haar_blocks(40 + i, n=14 + i % 3, nblocks=14) for i in range(4))]
+    assert max(len(g.qubits) for c in circs for g in c.gates) == 6
+    b = q.Batch([(c.n, c.gates) for c in circs], precision=0, small_max_n=12, tile_bits=13, max_fuse_k=6)
+    assert b.info()["tile_circuits"] == 4
+    b.launch()
+    for c, z in zip(circs, b.results()):
+        err = np.max(np.abs(z - orc.expect_z(orc.run_circuit(c))))
+        assert err <= 2e-5, (c.name, err)
+    b.close()
+
+
+@pytest.mark.gpu
 def test_batch_parameter_update(q):
     circs = small_batch(seed=6, count=10)
     b = q.Batch([(c.n, c.gates) for c in circs], precision=1, small_max_n=10, tile_bits=10)
