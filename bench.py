@@ -66,9 +66,10 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def traffic_for(kernel: str, workload: str, launches_bytes: float):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source; else None."""
+def profile_for(kernel: str, workload: str):
+    """The committed rocprofv3 summary of `kernel` on `workload` (HBM bytes per
+    launch from FETCH_SIZE/WRITE_SIZE, SQ counter figures), if it was taken on
+    the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
@@ -76,7 +77,7 @@ def traffic_for(kernel: str, workload: str, launches_bytes: float):
         d = json.load(fh)
     if d.get("source_hash") != kernel_source_hash():
         return None
-    return d.get("bytes_per_launch")
+    return d
 
 
 def cpu_baseline(circ, seconds: float):
@@ -696,8 +697,20 @@ def main() -> None:
     else:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(gbs / HBM_PEAK_GBS, 4)}
-    tr = traffic_for(dom, args.workload, bytes_launch)
-    roof["traffic"] = tr
+    pr = profile_for(dom, args.workload)
+    roof["traffic"] = pr.get("bytes_per_launch") if pr else None
+    if pr and pr.get("counters"):
+        c = pr["counters"]
+        # matrix-core work the kernel really issues (the three-product form
+        # runs 6·2^k flops per amplitude for k >= 4) and its busy fraction,
+        # from the committed SQ counter run of the same source
+        roof["counters"] = {"source": f"profiles/{dom}_{args.workload}.md",
+                            "mfma_busy_frac": round(c["mfma_busy_frac"], 4),
+                            "mfma_executed_tflops": round(c["mfma_exec_tflops"], 2),
+                            "mfma_executed_frac": round(c["mfma_exec_frac_of_peak"], 4),
+                            "valu_insts_per_launch": c["valu_insts_per_launch"],
+                            "lds_bank_conflict_frac": round(c["lds_bank_conflict_frac"], 4)}
+    roof["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
     roof["kernel"] = dom
     roof["timed_over"] = f"{args.steps} profiling-run steps after the timed plain steps (HIP events per pass)"
     roof["launches_per_step"] = d["launches"] // args.steps
