@@ -234,16 +234,19 @@ hipError_t enqueue(qops_batch_exec* e, hipStream_t s)
                                        e->d_out, e->lds_small, s);
     for (size_t k = 0; k < e->nodes.size() && er == hipSuccess; ++k) {
         const auto& nd = e->nodes[k];
+        // register-tile items: six waves per SIMD (the register body's
+        // 76-82 VGPRs allow that many) to hide the global loads and lane
+        // exchanges of the one-wave work-groups
         if (nd.kind == 0)
             er = launch_batch_reg(e->prec, nd.R, nd.W, nd.d, (int)nd.items.size(), e->d_circs, e->d_hdrs, e->d_ops,
-                                  e->d_coef, nd.pass, nd.lds, e->grid * 4, s);
+                                  e->d_coef, nd.pass, nd.lds, (e->grid * 12) >> nd.W, s);
         else
             er = launch_batch_pass(e->prec, nd.d, (int)nd.items.size(), e->d_circs, e->d_hdrs, e->d_ops, e->d_coef,
                                    nd.pass, nd.lds, e->grid, s);
     }
     if (er == hipSuccess)
         er = launch_batch_z(e->prec, e->d_zitems, (int)e->z_items.size(), e->d_big, (int)e->big_ids.size(), e->d_circs,
-                            e->d_part, e->d_out, e->grid, s);
+                            e->d_part, e->d_out, e->grid * 4, s);
     return er;
 }
 
