@@ -7,8 +7,10 @@ width 4..7, qubit remap on/off, block fusion width 1..4) and executed once as
 a profiling run; every
 fused pass is one sample (64 features -> log seconds, scaled to 30 qubits).  Circuits are split
 90/10 into training and held-out sets.  The plain cost table is the
-least-squares fit the library makes to the training profile; the learned one
-is the perceptron trained here.  Both are scored on the held-out passes.
+library's per-shape table of median times (kernel kind, tile width,
+register/wave split, widest block, operation count) fitted to the same
+training passes; the learned one is the perceptron trained here.  Both are
+scored on the held-out passes.
 
     python -m paper_2410_09326_amd.costmodel_train --circuits 600 --out paper_2410_09326_amd/models
 """
