@@ -748,26 +748,43 @@ def main() -> None:
     }
     sim.close()
     torch.cuda.empty_cache()
+    t_leg = time.perf_counter()
+
+    def leg_done(name):
+        # one line per finished leg on stderr (the JSON line stays alone on stdout)
+        nonlocal t_leg
+        now = time.perf_counter()
+        print(f"[bench] {name} done in {now - t_leg:.1f} s", file=sys.stderr, flush=True)
+        t_leg = now
+
+    leg_done("headline")
     if not args.no_swap_eval:
         out["swap_modes"] = swap_modes()
         torch.cuda.empty_cache()
+        leg_done("swap_modes")
     if not args.no_tier_eval:
         out["host_tier"] = host_tier(args.tier_qubits)
+        leg_done("host_tier")
     if not args.no_learned_eval:
         out["learned_vs_plain"] = learned_vs_plain(args.eval_circuits)
+        leg_done("learned_vs_plain")
     if not args.no_batch_eval:
         out["batch_sweep"] = batch_sweep(args.batch_reps, batch_shape)
+        leg_done("batch_sweep")
     if not args.no_qaoa_eval:
         out["qaoa_sweep"] = qaoa_sweep()
+        leg_done("qaoa_sweep")
     cb = None
     if not args.no_cpu_baseline:
         cb = cpu_baseline(circ, args.cpu_seconds)
         out["cpu_baseline"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in cb.items()
                                if k in ("value", "unit", "cores", "kind", "sample")}
+        leg_done("cpu_baseline")
     else:
         out["cpu_baseline"] = None
     if not args.no_oracle_timing:
         out["oracle_timing"] = oracle_timing(out, cb if args.workload == "haar30" else None)
+        leg_done("oracle_timing")
     print(json.dumps(out), flush=True)
 
 
