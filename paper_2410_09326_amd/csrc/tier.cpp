@@ -477,6 +477,13 @@ int32_t qops_tier_create(int32_t n, int32_t precision, int32_t global_bits, int3
         const size_t segb = ((size_t)1 << t->nloc) * amp_size(precision);
         t->seg.assign((size_t)1 << global_bits, nullptr);
         auto cleanup = [&]() {
+            for (int s = 0; s < 2; ++s) {
+                if (t->loaded[s]) (void)hipEventDestroy(t->loaded[s]);
+                if (t->computed[s]) (void)hipEventDestroy(t->computed[s]);
+                if (t->stored[s]) (void)hipEventDestroy(t->stored[s]);
+            }
+            if (t->copy_in) (void)hipStreamDestroy(t->copy_in);
+            if (t->copy_out) (void)hipStreamDestroy(t->copy_out);
             for (void* d : t->dev)
                 if (d) (void)hipFree(d);
             if (t->host_owned)
