@@ -92,6 +92,23 @@ def test_hoisted_blocks_across_tiles(q, prec, limit):
     check(got, oracle_state(c), prec, f"hoisted limit={limit}")
 
 
+@pytest.mark.parametrize("limit", [0, 3])
+def test_five_qubit_blocks_with_controls_full_tile(q, limit):
+    """complex64 on 2^13-amplitude tiles, where 5-qubit blocks run the 32x32x2
+    form: two 5-qubit blocks per pass (one keeps its fragments in registers,
+    the other reads them from LDS), with controls on tile positions and on
+    bits outside the tile, and a 6-qubit block beside a 5-qubit one."""
+    rng = W.rng_for(53)
+    mk = lambda qs, cs=(): W.Gate("dense", tuple(qs), tuple(cs), (), W.haar_unitary(rng, 2 ** len(qs)))
+    gates = [mk((0, 3, 7, 9, 12)), mk((1, 2, 8, 10, 11), (4,)), mk((5, 6, 13, 14, 15), (0, 12)),
+             mk((2, 4, 9, 11, 13), (16,)), mk((0, 1, 5, 8, 12, 15)), mk((3, 6, 10, 14, 16), (2, 7)),
+             mk((1, 7, 11, 12, 16))]
+    c = W.Circuit(17, gates, x0=12345, name="wide5ctl17")
+    got, l2p = run_gpu(q, c, 0, limit)
+    check(got, oracle_state(c), 0, f"5-qubit blocks with controls limit={limit}")
+    assert np.array_equal(l2p, orc.expected_layout(c.n, c.gates))
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("limit", [1, 5])
 def test_register_tiles_and_sweeps_many_per_workgroup(q, prec, limit):
