@@ -1295,27 +1295,46 @@ tile_lds_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict__
     }
     // element e = 256 u + tid: bits 0..F-1 of tid are physical bits 0..F-1
     // (F = QOPS_LDS_FIXED_BITS, contiguous in memory), bits F..7 of tid
-    // select up_phys[0 .. 7-F], bit b of u selects up_phys[8-F+b]
+    // select up_phys[0 .. 7-F], bit b of u selects up_phys[8-F+b].
+    // P2 (full complex64 tiles): each thread moves two adjacent amplitudes
+    // with one 16-byte access, element e = 512 u + 2 tid + h: h and bits
+    // 0..F-2 of tid are physical bits 0..F-1, bits F-1..7 of tid select
+    // up_phys[0 .. 8-F], bit b of u selects up_phys[9-F+b].  Half the vector
+    // memory instructions per tile, so a wave's tile stores and the next
+    // tile's loads stay within the outstanding-access counter.
     constexpr int F = QOPS_LDS_FIXED_BITS;
-    const uint32_t tlow = (uint32_t)tid & ((1u << F) - 1u);
-    const uint64_t dep_thr = dep_up((uint32_t)(tid >> F), hp->up_phys, nup);
-    uint64_t ub[5];
+    constexpr bool P2 = FULL && sizeof(T) == 4;
+    constexpr int NU = P2 ? EPT / 2 : EPT;         // accesses per thread and tile
+    constexpr int TB = P2 ? F - 1 : F;              // tid bits inside the contiguous run
+    constexpr int UB0 = P2 ? 9 - F : 8 - F;         // up_phys index of u's bit 0
+    constexpr int NUB = P2 ? 4 : 5;                 // bits of u
+    const uint32_t tlow = ((uint32_t)tid & ((1u << TB) - 1u)) << (P2 ? 1 : 0);
+    const uint64_t dep_thr = dep_up((uint32_t)(tid >> TB), hp->up_phys, nup);
+    uint64_t ub[NUB];
 #pragma unroll
-    for (int b = 0; b < 5; ++b) ub[b] = (8 - F + b < nup) ? (1ull << hp->up_phys[8 - F + b]) : 0ull;
+    for (int b = 0; b < NUB; ++b) ub[b] = (UB0 + b < nup) ? (1ull << hp->up_phys[UB0 + b]) : 0ull;
     auto uoff = [&](int u) {
         uint64_t o = 0;
 #pragma unroll
-        for (int b = 0; b < 5; ++b)
+        for (int b = 0; b < NUB; ++b)
             if (u & (1 << b)) o += ub[b];
         return o;
     };
     const uint32_t tsw = swz((uint32_t)tid);
-    T pr[EPT], pi[EPT];
+    // P2: the pair of element 2 tid (+ 512 u) sits in LDS slots s and s ^ 1 with
+    // s = swz(512 u) ^ swz(2 tid); one 16-byte access covers both, in swapped
+    // order where bit 0 of swz(2 tid) (= bit 4 of tid) is set
+    const uint32_t psw = swz(2u * (uint32_t)tid) & ~1u;
+    const bool pswap = (tid >> 4) & 1;
+    float4 q2[P2 ? NU : 1];
+    T pr[P2 ? 1 : EPT], pi[P2 ? 1 : EPT];
     auto fetch = [&](uint64_t tile) {
         const V* __restrict__ src = st + tile_base(tile, hp) + tlow + dep_thr;
-        sfor<EPT>([&](auto uc) {
+        sfor<NU>([&](auto uc) {
             constexpr int u = decltype(uc)::value;
-            if (FULL || 256u * u < N) {
+            if constexpr (P2) {
+                q2[u] = *reinterpret_cast<const float4*>(src + uoff(u));
+            } else if (FULL || 256u * u < N) {
                 const V x = src[uoff(u)];
                 pr[u] = x.x;
                 pi[u] = x.y;
@@ -1329,9 +1348,17 @@ tile_lds_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict__
     __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
     for (; tile < ntiles; tile += gridDim.x) {
         const uint64_t base = tile_base(tile, hp);
-        sfor<EPT>([&](auto uc) {
+        sfor<NU>([&](auto uc) {
             constexpr int u = decltype(uc)::value;
-            if (FULL || 256u * u < N) {
+            if constexpr (P2) {
+                const float4 x = q2[u];
+                float4 w;
+                w.x = pswap ? x.z : x.x;
+                w.y = pswap ? x.w : x.y;
+                w.z = pswap ? x.x : x.z;
+                w.w = pswap ? x.y : x.w;
+                lds_put(reinterpret_cast<float4*>(smem_raw), (swz(512u * u) ^ psw) * 8u, w);
+            } else if (FULL || 256u * u < N) {
                 V x;
                 x.x = pr[u];
                 x.y = pi[u];
@@ -1376,9 +1403,19 @@ tile_lds_kernel(typename CxT<T>::V* __restrict__ st, const PassHdr* __restrict__
         }
         {
             V* __restrict__ dst = st + base + tlow + dep_thr;
-            sfor<EPT>([&](auto uc) {
+            sfor<NU>([&](auto uc) {
                 constexpr int u = decltype(uc)::value;
-                if (FULL || 256u * u < N) dst[uoff(u)] = lds[swz(256u * u) ^ tsw];
+                if constexpr (P2) {
+                    const float4 x = lds_at(reinterpret_cast<const float4*>(smem_raw), (swz(512u * u) ^ psw) * 8u);
+                    float4 w;
+                    w.x = pswap ? x.z : x.x;
+                    w.y = pswap ? x.w : x.y;
+                    w.z = pswap ? x.x : x.z;
+                    w.w = pswap ? x.y : x.w;
+                    *reinterpret_cast<float4*>(dst + uoff(u)) = w;
+                } else if (FULL || 256u * u < N) {
+                    dst[uoff(u)] = lds[swz(256u * u) ^ tsw];
+                }
             });
         }
         __syncthreads();
