@@ -180,6 +180,16 @@ typedef struct qops_plan_opts {
                                       SWAP; 1 = on, -1 = off, 0 = the paper's
                                       rule (on when T gates exceed 10% of the
                                       gates).  Exact, global phase included.  */
+    int32_t merge_blocks;          /* priced merging of dense blocks (paper
+                                      Sec. III-C/D, profile-guided choice of
+                                      what to combine): two uncontrolled dense
+                                      blocks that commute past the operations
+                                      between them become one block on the
+                                      union of their qubits (<= 6) when the
+                                      measured per-block cost of the union is
+                                      below the sum of theirs.  1 = on,
+                                      -1 = off, 0 = on for complex64 (whose
+                                      per-width costs the table holds)        */
 } qops_plan_opts;
 
 /* Fills opts with the defaults listed above (Sec. III-D: which optimisations

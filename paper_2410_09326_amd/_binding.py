@@ -44,7 +44,7 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("swap_mode", ctypes.c_int32), ("tile_upper", ctypes.c_int32),
                 ("max_fuse_k", ctypes.c_int32), ("use_mfma", ctypes.c_int32), ("check_unitary", ctypes.c_int32),
                 ("remap", ctypes.c_int32), ("profile", ctypes.c_void_p), ("model", ctypes.c_void_p),
-                ("fold_rotations", ctypes.c_int32)]
+                ("fold_rotations", ctypes.c_int32), ("merge_blocks", ctypes.c_int32)]
 
 
 class PlanStats(ctypes.Structure):
@@ -272,7 +272,7 @@ def plan_opts_from(**opts) -> PlanOpts:
 
 def plan_opts(mode: int = PLAN_FUSED, swap_mode: int = SWAP_VIRTUAL, tile_upper: int = 0, max_fuse_k: int = 0,
               use_mfma: int = 1, check_unitary: int = 0, remap: int = 0, profile=None, model=None,
-              fold_rotations: int = 0) -> PlanOpts:
+              fold_rotations: int = 0, merge_blocks: int = 0) -> PlanOpts:
     o = PlanOpts()
     check(lib().qops_plan_opts_default(ctypes.byref(o)))
     o.mode, o.swap_mode, o.tile_upper = mode, swap_mode, tile_upper
@@ -280,6 +280,7 @@ def plan_opts(mode: int = PLAN_FUSED, swap_mode: int = SWAP_VIRTUAL, tile_upper:
     o.profile = profile.handle if profile is not None else None
     o.model = model.handle if model is not None else None
     o.fold_rotations = fold_rotations
+    o.merge_blocks = merge_blocks
     return o
 
 

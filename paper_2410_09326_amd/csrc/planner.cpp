@@ -338,6 +338,87 @@ static void block_apply(std::vector<cd>& M, const std::vector<int>& Q, const LOp
 // the first op not yet placed and scans ahead, taking ops that fit and
 // commute with every op skipped so far (the same rule as pass packing).
 // Blocks of a single op, and blocks of diagonals only, are kept as they are.
+// Priced merging of dense blocks (the profile-guided choice of which gates
+// to combine, Sec. III-C/D).  Cost of one block of k qubits in a complex64
+// LDS tile pass, in ms at 30 qubits: the marginal pass time per block,
+// regressed from the per-pass times of a profiling run of Haar-block
+// circuits (k = 2 on the vector ALU; k = 3 in the real embedding; k >= 4 in
+// the three-product form; k = 5 in the 32x32x2 one).  Only the ratios
+// matter: every cost scales with the state size.
+static const double kBlockCostC64[7] = {0.0, 0.30, 0.69, 0.94, 1.09, 1.69, 2.98};
+
+// Greedy, like fuse_blocks, over uncontrolled dense blocks of 2..6 qubits:
+// a block absorbs a later one that commutes with every operation skipped in
+// between when the union (<= 6 qubits) is priced below the two apart.  The
+// merged matrix is the FP64 product in circuit order.
+static void merge_dense_priced(std::vector<LOp>& ops, const double* cost)
+{
+    const size_t n = ops.size();
+    const size_t window = 64;
+    auto mergeable = [](const LOp& o) { return o.kind == LOp::DENSE && o.cmask == 0 && o.k >= 2 && !o.dead; };
+    std::vector<char> placed(n, 0);
+    std::vector<LOp> out;
+    out.reserve(n);
+    for (size_t first = 0; first < n; ++first) {
+        if (placed[first]) continue;
+        placed[first] = 1;
+        const LOp& a = ops[first];
+        if (!mergeable(a)) {
+            out.push_back(a);
+            continue;
+        }
+        uint64_t Qm = a.touch();
+        std::vector<size_t> mem = {first};
+        uint64_t skip_touch = 0, skip_nd = 0;
+        const size_t stop = std::min(n, first + 1 + window);
+        for (size_t j = first + 1; j < stop; ++j) {
+            if (placed[j] || ops[j].dead) continue;
+            const LOp& o = ops[j];
+            if (o.kind == LOp::PSWAP) break;
+            const uint64_t tj = o.touch(), nj = o.tmask();
+            const bool commutes = (nj & skip_touch) == 0 && (tj & skip_nd) == 0;
+            const int ku = __builtin_popcountll(Qm | tj);
+            if (commutes && mergeable(o) && ku <= 6 &&
+                cost[ku] < cost[__builtin_popcountll(Qm)] + cost[__builtin_popcountll(tj)]) {
+                Qm |= tj;
+                mem.push_back(j);
+                placed[j] = 1;
+            } else {
+                skip_touch |= tj;
+                skip_nd |= nj;
+                if (__builtin_popcountll(skip_nd) >= 64) break;
+            }
+        }
+        if (mem.size() == 1) {
+            out.push_back(a);
+            continue;
+        }
+        // the first block's qubit order first, then the new qubits in order
+        std::vector<int> Q;
+        for (int j = 0; j < a.k; ++j) Q.push_back(a.t[j]);
+        for (size_t mi = 1; mi < mem.size(); ++mi)
+            for (int j = 0; j < ops[mem[mi]].k; ++j)
+                if (std::find(Q.begin(), Q.end(), ops[mem[mi]].t[j]) == Q.end()) Q.push_back(ops[mem[mi]].t[j]);
+        const uint32_t D = 1u << Q.size();
+        LOp f;
+        f.kind = LOp::DENSE;
+        f.k = (int)Q.size();
+        for (int j = 0; j < f.k; ++j) f.t[j] = Q[j];
+        f.cmask = 0;
+        f.m.assign((size_t)D * D, cd(0));
+        for (uint32_t i = 0; i < D; ++i) f.m[(size_t)i * D + i] = 1;
+        f.gate = a.gate;
+        f.gkind = QOPS_DENSE;
+        f.nmerged = 0;
+        for (size_t j : mem) {
+            block_apply(f.m, Q, ops[j]);
+            f.nmerged += ops[j].nmerged;
+        }
+        out.push_back(std::move(f));
+    }
+    ops.swap(out);
+}
+
 static void fuse_blocks(std::vector<LOp>& ops, int kmax)
 {
     if (kmax < 2) return;
@@ -1347,6 +1428,8 @@ static Err finish_plan(Plan& p, std::vector<LOp>& lowered, std::chrono::steady_c
         p.lops.swap(lowered);
     } else {
         merge_ops(lowered, p.lops);
+        if (par.merge_blocks > 0 || (par.merge_blocks == 0 && p.prec == QOPS_C64))
+            merge_dense_priced(p.lops, kBlockCostC64);
         fuse_blocks(p.lops, std::min(par.max_fuse_k, 6));
     }
     pack(p);

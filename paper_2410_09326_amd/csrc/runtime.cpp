@@ -173,6 +173,7 @@ PlanParams params_from(const qops_plan_opts* o, int n, int prec)
     }
     par.max_fuse_k = o->max_fuse_k > 0 ? o->max_fuse_k : 1;
     par.fold = o->fold_rotations > 0 ? 1 : (o->fold_rotations < 0 ? -1 : 0);
+    par.merge_blocks = o->merge_blocks > 0 ? 1 : (o->merge_blocks < 0 ? -1 : 0);
     par.remap = o->remap;
     par.use_mfma = o->use_mfma;
     par.check_unitary = o->check_unitary;

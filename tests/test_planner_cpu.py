@@ -89,6 +89,27 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("prec,mb", [(q.C64, 0), (q.C128, 1)])
+def test_priced_block_merging_reproduces_circuit(prec, mb):
+    """Priced merging of dense blocks (on by default for complex64): the plan
+    has fewer dense blocks than the circuit, every source gate is folded into
+    exactly one operation, and the lowered operations replayed with the
+    oracle's matrix routine give the circuit's state."""
+    c = W.haar_blocks(21, n=14, nblocks=40)
+    plan = q.Plan(c.n, c.gates, precision=prec, merge_blocks=mb)
+    off = q.Plan(c.n, c.gates, precision=prec, merge_blocks=-1)
+    ops = plan.ops()
+    assert len(ops) < len(off.ops())
+    assert max(o["k"] for o in ops) <= 6
+    assert sum(o["n_merged"] for o in ops) == len(c.gates)
+    got = physical_replay(c.n, plan, c.x0)
+    assert np.max(np.abs(got - orc.run_circuit(c))) <= 1e-12
+    # merged blocks are unitary products of their parts: a merged block's
+    # width is at most the sum of two source widths and at least the wider
+    ks = sorted(len(g.qubits) for g in c.gates)
+    assert min(o["k"] for o in ops) >= ks[0]
+
+
 @pytest.mark.parametrize("name,make", CASES)
 @pytest.mark.parametrize("mode", [q.PLAN_FUSED, q.PLAN_GATEWISE])
 @pytest.mark.parametrize("swap_mode", [q.SWAP_VIRTUAL, q.SWAP_PHYSICAL])
