@@ -717,6 +717,15 @@ def main() -> None:
     roof["avg_launch_ms"] = round(avg_s * 1e3, 4)
     roof["alg_bytes_per_launch"] = bytes_launch
     roof["alg_flops_per_launch"] = flops_launch
+    # the same rate on the input circuit's own blocks (8·2^k·2^n per dense
+    # gate): the plan merges blocks, which raises the flops it executes
+    dense_in = [g for g in circ.gates if g.kind == "dense" and not g.controls]
+    if dom in MATRIX_KERNELS and len(dense_in) == len(circ.gates):
+        circ_flops = sum(8.0 * 2 ** len(g.qubits) * 2 ** n for g in dense_in)
+        cf_launch = circ_flops / roof["launches_per_step"]
+        roof["circuit_flops_per_launch"] = cf_launch
+        roof["circuit_tflops"] = round(cf_launch / avg_s / 1e12, 2)
+        roof["circuit_frac"] = round(cf_launch / avg_s / 1e12 / fpeak, 4)
 
     step_bytes = sum(p["bytes_alg"] for p in passes) + 2 * (2 ** n) * amp   # + init write, reduction read
     value = step_bytes / (ms * 1e-3) / 1e9
