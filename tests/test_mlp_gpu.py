@@ -25,7 +25,7 @@ def test_model_file_roundtrip_cpu():
         p, mu2, sd2 = m2.params()
     assert np.array_equal(p, p0) and np.array_equal(mu2, mu) and np.array_equal(sd2, sd)
     assert q.CostModel.num_params() == p0.size
-    # the flat layout round-trips through the reference's dict form
+    # the flat layout round-trips through the FP64 oracle's dict form
     assert np.array_equal(mo.flatten(mo.unflatten(p0.astype(np.float64))), p0.astype(np.float64))
 
 
