@@ -710,6 +710,11 @@ def main() -> None:
                             "mfma_executed_frac": round(c["mfma_exec_frac_of_peak"], 4),
                             "valu_insts_per_launch": c["valu_insts_per_launch"],
                             "lds_bank_conflict_frac": round(c["lds_bank_conflict_frac"], 4)}
+        if "valu_fp_busy_frac" in c:
+            # share of the SIMDs' cycles the vector FP pipe is busy (4 cycles
+            # per wave64 FMA/MUL/ADD): the bound of the vector-ALU kernels
+            roof["counters"]["valu_fp_insts_per_launch"] = c["valu_fp_insts_per_launch"]
+            roof["counters"]["valu_fp_busy_frac"] = round(c["valu_fp_busy_frac"], 4)
     roof["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
     roof["kernel"] = dom
     roof["timed_over"] = f"{args.steps} profiling-run steps after the timed plain steps (HIP events per pass)"
