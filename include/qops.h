@@ -187,9 +187,9 @@ typedef struct qops_plan_opts {
                                       between them become one block on the
                                       union of their qubits (<= 6) when the
                                       measured per-block cost of the union is
-                                      below the sum of theirs.  1 = on,
-                                      -1 = off, 0 = on for complex64 (whose
-                                      per-width costs the table holds)        */
+                                      below the sum of theirs (a per-width
+                                      cost table for each precision).  1 or
+                                      0 (the default) = on, -1 = off.        */
 } qops_plan_opts;
 
 /* Fills opts with the defaults listed above (Sec. III-D: which optimisations

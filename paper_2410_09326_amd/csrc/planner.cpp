@@ -332,20 +332,17 @@ static void block_apply(std::vector<cd>& M, const std::vector<int>& Q, const LOp
     }
 }
 
-// k-qubit block fusion: ops whose bits (targets, controls, table bits) fit a
-// common set of at most kmax physical bits become one dense 2^k x 2^k block,
-// the FP64 product of the ops embedded on that set.  Each block opens with
-// the first op not yet placed and scans ahead, taking ops that fit and
-// commute with every op skipped so far (the same rule as pass packing).
-// Blocks of a single op, and blocks of diagonals only, are kept as they are.
 // Priced merging of dense blocks (the profile-guided choice of which gates
-// to combine, Sec. III-C/D).  Cost of one block of k qubits in a complex64
-// LDS tile pass, in ms at 30 qubits: the marginal pass time per block,
+// to combine, Sec. III-C/D).  Cost of one block of k qubits in an LDS tile
+// pass, in ms at 30 qubits: the marginal pass time per block.  Complex64:
 // regressed from the per-pass times of a profiling run of Haar-block
 // circuits (k = 2 on the vector ALU; k = 3 in the real embedding; k >= 4 in
-// the three-product form; k = 5 in the 32x32x2 one).  Only the ratios
-// matter: every cost scales with the state size.
+// the three-product form; k = 5 in the 32x32x2 one).  Complex128: from
+// circuits of 24 blocks of one width, the pass time above the memory phase
+// (6.2 ms) per block.  Only the ratios matter: every cost scales with the
+// state size.  Entry 1 is never used (merging takes blocks of 2 or more).
 static const double kBlockCostC64[7] = {0.0, 0.30, 0.69, 0.94, 1.09, 1.69, 2.98};
+static const double kBlockCostC128[7] = {0.0, 1.0, 1.74, 1.98, 2.20, 3.90, 5.98};
 
 // Greedy, like fuse_blocks, over uncontrolled dense blocks of 2..6 qubits:
 // a block absorbs a later one that commutes with every operation skipped in
@@ -419,6 +416,12 @@ static void merge_dense_priced(std::vector<LOp>& ops, const double* cost)
     ops.swap(out);
 }
 
+// k-qubit block fusion: ops whose bits (targets, controls, table bits) fit a
+// common set of at most kmax physical bits become one dense 2^k x 2^k block,
+// the FP64 product of the ops embedded on that set.  Each block opens with
+// the first op not yet placed and scans ahead, taking ops that fit and
+// commute with every op skipped so far (the same rule as pass packing).
+// Blocks of a single op, and blocks of diagonals only, are kept as they are.
 static void fuse_blocks(std::vector<LOp>& ops, int kmax)
 {
     if (kmax < 2) return;
@@ -1428,8 +1431,8 @@ static Err finish_plan(Plan& p, std::vector<LOp>& lowered, std::chrono::steady_c
         p.lops.swap(lowered);
     } else {
         merge_ops(lowered, p.lops);
-        if (par.merge_blocks > 0 || (par.merge_blocks == 0 && p.prec == QOPS_C64))
-            merge_dense_priced(p.lops, kBlockCostC64);
+        if (par.merge_blocks >= 0)
+            merge_dense_priced(p.lops, p.prec == QOPS_C64 ? kBlockCostC64 : kBlockCostC128);
         fuse_blocks(p.lops, std::min(par.max_fuse_k, 6));
     }
     pack(p);

@@ -55,7 +55,7 @@ struct PlanParams {
     int remap = 0;             // move the most-targeted qubits into physical bits 0..5 first
     int force_lds = 0;         // every tile pass is an LDS pass (batched executor)
     int fold = 0;              // rotation folding: 1 on, -1 off, 0 by the T-gate rule
-    int merge_blocks = 0;      // priced dense-block merging: 1 on, -1 off, 0 on for complex64
+    int merge_blocks = 0;      // priced dense-block merging: -1 off, else on
 };
 
 struct Plan {
