@@ -89,9 +89,9 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("prec,mb", [(q.C64, 0), (q.C128, 1)])
+@pytest.mark.parametrize("prec,mb", [(q.C64, 0), (q.C128, 0), (q.C128, 1)])
 def test_priced_block_merging_reproduces_circuit(prec, mb):
-    """Priced merging of dense blocks (on by default for complex64): the plan
+    """Priced merging of dense blocks (on by default, a cost table per precision): the plan
     has fewer dense blocks than the circuit, every source gate is folded into
     exactly one operation, and the lowered operations replayed with the
     oracle's matrix routine give the circuit's state."""
