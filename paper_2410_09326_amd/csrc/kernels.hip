@@ -1924,7 +1924,7 @@ __device__ __forceinline__ uint32_t compress_sel(uint64_t x, const PosArr& pa, i
 
 template <typename T>
 __global__ void __launch_bounds__(256)
-probs_part_kernel(const typename CxT<T>::V* __restrict__ st, int n, int m, PosArr pa, int s, int m_lo,
+probs_part_kernel(const typename CxT<T>::V* __restrict__ st, int m, PosArr pa, int s, int m_lo,
                   uint32_t sel_lo, uint32_t sel12, int m12, uint32_t mask12, double* __restrict__ part)
 {
     __shared__ double tab[4096];
@@ -1995,10 +1995,7 @@ probs_reduce_kernel(const double* __restrict__ part, int n, int m, PosArr pa, in
 
 size_t probs_scratch_doubles(int n, int m, const int* pos)
 {
-    if (m == n) return 0;
-    int m12 = 0;
-    for (int j = 0; j < m; ++j) m12 += pos[j] < 12 ? 1 : 0;
-    if (m > 12) return 0;
+    if (m == n || m > 12) return 0;
     const ProbGeom g = prob_geom(n, m, pos);
     return (size_t(1) << (n - g.s)) * (size_t(1) << g.m_lo);
 }
@@ -2045,10 +2042,10 @@ hipError_t launch_probs(int prec, const void* state, int n, int m, const int* po
     const unsigned nb = 1u << (n - g.s);
     if (prec == 0)
         hipLaunchKernelGGL(probs_part_kernel<float>, dim3(nb), dim3(256), 0, st, reinterpret_cast<const float2*>(state),
-                           n, m, pa, g.s, g.m_lo, sel_lo, sel12, m12, mask12, scratch);
+                           m, pa, g.s, g.m_lo, sel_lo, sel12, m12, mask12, scratch);
     else
         hipLaunchKernelGGL(probs_part_kernel<double>, dim3(nb), dim3(256), 0, st,
-                           reinterpret_cast<const double2*>(state), n, m, pa, g.s, g.m_lo, sel_lo, sel12, m12, mask12,
+                           reinterpret_cast<const double2*>(state), m, pa, g.s, g.m_lo, sel_lo, sel12, m12, mask12,
                            scratch);
     const uint64_t ny = 1ull << m;
     hipLaunchKernelGGL(probs_reduce_kernel<float>, dim3(grid_for(ny, 256)), dim3(256), 0, st, scratch, n, m, pa, g.s,
