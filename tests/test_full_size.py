@@ -16,7 +16,10 @@ properties that hold at any size (the FP64 oracle cannot hold these states):
   cost-model plans: <Z_i> against the complex128 run;
 * the first blocks of the 30-qubit Haar-block benchmark circuit in the
   default plan and launch against the FP64 oracle itself, element by
-  element (16 GiB of host memory for the oracle's state).
+  element (16 GiB of host memory for the oracle's state);
+* the largest states the library accepts (34 qubits complex64, 33 qubits
+  complex128: 128 GiB, indices past 2^32): a circuit whose <Z_q> has a closed
+  form (pinned against the oracle at small n), and the norm.
 """
 import numpy as np
 import pytest
@@ -212,3 +215,26 @@ def test_eval32_priced_plans_agree_with_c128(q):
         sim.run(q.Plan(32, c.gates, precision=q.C64, mode=mode, **kw))
         assert np.max(np.abs(sim.expect_z() - zref)) <= 1e-5
     sim.close()
+
+
+@pytest.mark.parametrize("n,prec", [(34, 0), (33, 1)])
+def test_largest_states_closed_form(q, n, prec):
+    """RY layers, Kronecker-product RY blocks of 2..6 qubits (register and
+    LDS tile passes, matrix cores), diagonals and virtual SWAPs on the
+    largest state of each precision: <Z_q> = cos of the summed RY angles."""
+    import torch
+    from product_state import product_state_circuit
+    c, z = product_state_circuit(n, 40 + n)
+    sim = q.Simulator(n, prec)
+    try:
+        sim.init_basis(0)
+        sim.run(q.Plan(n, c.gates, precision=prec))
+        got = sim.expect_z()
+        nrm = sim.norm()
+    finally:
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    tol = 2e-5 if prec == q.C64 else 1e-10
+    assert abs(nrm - 1.0) <= tol
+    assert np.max(np.abs(got - z)) <= tol

@@ -204,6 +204,18 @@ def test_ry_cz_ladder_expectations(n):
     assert np.max(np.abs(orc.expect_z(psi) - np.cos(th))) <= 1e-13
 
 
+@pytest.mark.parametrize("n,seed", [(8, 1), (11, 2), (13, 3)])
+def test_product_state_circuit_expectations(n, seed):
+    """The closed form the largest-size GPU test relies on: RY layers,
+    Kronecker-product RY blocks, diagonals and SWAPs give <Z_q> = cos of the
+    summed RY angles of the qubit state that q holds."""
+    from product_state import product_state_circuit
+    c, z = product_state_circuit(n, seed)
+    psi = orc.run_circuit(c)
+    assert abs(np.vdot(psi, psi).real - 1.0) <= 1e-13
+    assert np.max(np.abs(orc.expect_z(psi) - z)) <= 1e-13
+
+
 @pytest.mark.parametrize("seed", range(5))
 def test_circuit_then_inverse(seed):
     n = 7
