@@ -234,9 +234,10 @@ hipError_t enqueue(qops_batch_exec* e, hipStream_t s)
                                        e->d_out, e->lds_small, s);
     for (size_t k = 0; k < e->nodes.size() && er == hipSuccess; ++k) {
         const auto& nd = e->nodes[k];
-        // register-tile items: six waves per SIMD (the register body's
-        // 76-82 VGPRs allow that many) to hide the global loads and lane
-        // exchanges of the one-wave work-groups
+        // register-tile items: 6144 one-wave work-groups (six per SIMD; as
+        // many as the body's registers let reside: three at 148 VGPRs with
+        // five register bits, six at 79-82 VGPRs with four) to hide the
+        // global loads and lane exchanges
         if (nd.kind == 0)
             er = launch_batch_reg(e->prec, nd.R, nd.W, nd.d, (int)nd.items.size(), e->d_circs, e->d_hdrs, e->d_ops,
                                   e->d_coef, nd.pass, nd.lds, (e->grid * 12) >> nd.W, s);
