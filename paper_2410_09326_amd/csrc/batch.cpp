@@ -236,7 +236,7 @@ hipError_t enqueue(qops_batch_exec* e, hipStream_t s)
         const auto& nd = e->nodes[k];
         // register-tile items: 6144 one-wave work-groups (six per SIMD; as
         // many as the body's registers let reside: three at 148 VGPRs with
-        // five register bits, six at 79-82 VGPRs with four) to hide the
+        // five register bits, six at 79-80 VGPRs with four) to hide the
         // global loads and lane exchanges
         if (nd.kind == 0)
             er = launch_batch_reg(e->prec, nd.R, nd.W, nd.d, (int)nd.items.size(), e->d_circs, e->d_hdrs, e->d_ops,
