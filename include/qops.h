@@ -180,10 +180,12 @@ typedef struct qops_plan_opts {
                                       SWAP; 1 = on, -1 = off, 0 = the paper's
                                       rule (on when T gates exceed 10% of the
                                       gates).  Exact, global phase included.  */
-    int32_t merge_blocks;          /* priced merging of dense blocks (paper
-                                      Sec. III-C/D, profile-guided choice of
-                                      what to combine): two uncontrolled dense
-                                      blocks that commute past the operations
+    int32_t merge_blocks;          /* priced merging of dense blocks (the
+                                      two-qubit block merging of the paper's
+                                      all-on configuration, Sec. IV,
+                                      generalised to <= 6 qubits and priced
+                                      as in Sec. III-C/D): two uncontrolled
+                                      dense blocks that commute past the operations
                                       between them become one block on the
                                       union of their qubits (<= 6) when the
                                       measured per-block cost of the union is
